@@ -1,0 +1,89 @@
+"""Rollout loss and its FP64 central finite differences (differentiable dynamics, Sec. III-A).
+
+The paper differentiates its dynamics through autograd; the device path uses
+hand-written adjoints.  The oracle provides the reference derivative the plain
+way: central differences of an FP64 rollout.
+
+Loss (the obstacle-proximity + goal loss of the differentiable workload; the
+paper fixes none, this reading is used):
+    L = sum_agents sum_{k=1..H} [ mean_pixels exp(-D_k / d0) + w_goal |p_k - goal|^2 ],
+with D_k the depth image rendered at the state after step k, d0 = 1 m and
+w_goal = 0.01.  Missed pixels have the constant miss depth.
+"""
+import numpy as np
+
+from . import dynamics, render
+
+
+def rollout_loss(state0, actions, params, scene, goals, view, d0=1.0, w_goal=0.01, return_ids=False):
+    """L(s0, a_0..a_{H-1}) in FP64; optionally the per-step hit ids (for tie screening)."""
+    s = np.asarray(state0, dtype=np.float64)
+    goals = np.asarray(goals, dtype=np.float64)
+    total = 0.0
+    ids = []
+    for a in actions:
+        s = dynamics.step(s, a, params)
+        for i in range(s.shape[0]):
+            r = render.render_view(s[i], scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
+                                   view.get("miss_depth"), with_mask=False)
+            total += float(np.mean(np.exp(-r["depth"] / d0)))
+            if return_ids:
+                ids.append(r["id"])
+        total += w_goal * float(np.sum((s[:, 0:3] - goals) ** 2))
+    if return_ids:
+        return total, np.stack(ids) if ids else np.zeros((0,))
+    return total
+
+
+def central_difference(fun, x, direction, h=1e-6):
+    """(f(x + h u) - f(x - h u)) / (2h) for a flat FP64 vector x and direction u."""
+    x = np.asarray(x, dtype=np.float64)
+    u = np.asarray(direction, dtype=np.float64)
+    return (fun(x + h * u) - fun(x - h * u)) / (2.0 * h)
+
+
+def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_actions, h=1e-6, **kw):
+    """Directional derivative of the rollout loss along (u_state, u_actions) by central differences.
+
+    Returns (derivative, ids_stable): ids_stable is False when any pixel's hit
+    triangle differs between the +h and -h rollouts (the derivative is then not
+    defined by a single smooth branch and the direction should be discarded).
+    """
+    s0 = np.asarray(state0, dtype=np.float64)
+    a = np.asarray(actions, dtype=np.float64)
+    lp, idp = rollout_loss(s0 + h * u_state, a + h * u_actions, params, scene, goals, view, return_ids=True, **kw)
+    lm, idm = rollout_loss(s0 - h * u_state, a - h * u_actions, params, scene, goals, view, return_ids=True, **kw)
+    return (lp - lm) / (2.0 * h), bool(np.array_equal(idp, idm))
+
+
+def step_jacobian(state, action, params, h=1e-6):
+    """Central-difference Jacobians of one control step: d s' / d s [N,17,17] and d s' / d a [N,17,4]."""
+    s = np.asarray(state, dtype=np.float64)
+    a = np.asarray(action, dtype=np.float64)
+    n = s.shape[0]
+    js = np.empty((n, 17, 17))
+    ja = np.empty((n, 17, 4))
+    for j in range(17):
+        e = np.zeros_like(s)
+        e[:, j] = h
+        js[:, :, j] = (dynamics.step(s + e, a, params) - dynamics.step(s - e, a, params)) / (2 * h)
+    for j in range(4):
+        e = np.zeros_like(a)
+        e[:, j] = h
+        ja[:, :, j] = (dynamics.step(s, a + e, params) - dynamics.step(s, a - e, params)) / (2 * h)
+    return js, ja
+
+
+def depth_pose_gradient(state_row, scene, view, pixels, h=1e-6):
+    """Central differences of each listed pixel's depth with respect to p (3) and q (4): [P, 7]."""
+    s = np.asarray(state_row, dtype=np.float64)
+    g = np.empty((len(pixels), 7))
+    for j in range(7):
+        e = np.zeros(17)
+        e[j] = h
+        dp = render.render_view(s + e, scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
+                                view.get("miss_depth"), with_mask=False, pixels=pixels)["depth"]
+        dm = render.render_view(s - e, scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
+                                view.get("miss_depth"), with_mask=False, pixels=pixels)["depth"]
+        g[:, j] = (dp - dm) / (2 * h)
+    return g

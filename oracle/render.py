@@ -1,0 +1,174 @@
+"""FP64 pinhole camera and brute-force closest-hit render (Sec. III-B).
+
+Readings of what the paper leaves open (it rasterises with Habitat-Sim and
+gives no camera model):
+  * The camera sits at the body origin: optical axis +x_B, image right -y_B,
+    image up +z_B.  Pixel (row r from the top, column c from the left) of an
+    H x W image with horizontal field of view hfov looks along
+        d_B = (1, -u, v),  u = (2 (c + 1/2) / W - 1) tan(hfov/2),
+                           v = (1 - 2 (r + 1/2) / H) tan(hfov/2) H / W,
+    and d = R(q) d_B in the world frame.  Because the forward component of d_B
+    is 1, the hit distance t along d is the planar (z-buffer) depth.
+  * near = 0.01 m, far = 100 m; hits outside [near, far] are ignored; a miss
+    gives depth = miss_depth, id = -1, colour (0, 0, 0).
+  * Colour is the flat per-triangle uint8 RGB of the hit triangle.
+The brute-force caster itself is ``brute.c`` (every ray against every triangle).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "brute.c")
+_LIB = os.path.join(_HERE, "liboracle_brute.so")
+_lib = None
+
+
+def build_library(force=False):
+    """Compile brute.c with gcc (FP64, no contraction, OpenMP) into oracle/liboracle_brute.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build_library()
+        lib = ctypes.CDLL(_LIB)
+        d, i64, i32 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_cast.argtypes = [ctypes.c_int64, d, d, ctypes.c_int64, d, d, d, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, d, i64, d, d, d, i32, i32]
+        lib.oracle_cast.restype = None
+        lib.oracle_closest_point.argtypes = [ctypes.c_int64, d, ctypes.c_int64, d, d, d, d, d, i64]
+        lib.oracle_closest_point.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def triangle_vertices(verts, tris):
+    v = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tris, dtype=np.int64)
+    return (np.ascontiguousarray(v[t[:, 0]]), np.ascontiguousarray(v[t[:, 1]]), np.ascontiguousarray(v[t[:, 2]]))
+
+
+def cast(orig, dirs, verts, tris, near=0.01, far=100.0, with_mask=True):
+    """Brute-force closest hit of rays [R,3] (origins [R,3] or [3]) against all triangles.
+
+    Returns a dict of per-ray arrays: t (inf on miss), id (-1 on miss) and, with
+    with_mask, t2, edge_hit, near_miss, boundary, plus 'threads'.
+    """
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+    n = dirs.shape[0]
+    orig = np.ascontiguousarray(np.broadcast_to(np.asarray(orig, dtype=np.float64).reshape(-1, 3), (n, 3)))
+    v0, v1, v2 = triangle_vertices(verts, tris)
+    lib = _load()
+    out = {k: np.empty(n) for k in ("t", "t2", "edge_hit", "near_miss")}
+    out["id"] = np.empty(n, dtype=np.int64)
+    out["boundary"] = np.zeros(n, dtype=np.int32)
+    th = np.zeros(1, dtype=np.int32)
+    d = ctypes.c_double
+    lib.oracle_cast(n, _p(orig, d), _p(dirs, d), v0.shape[0], _p(v0, d), _p(v1, d), _p(v2, d), near, far,
+                    1 if with_mask else 0, _p(out["t"], d), _p(out["id"], ctypes.c_int64), _p(out["t2"], d),
+                    _p(out["edge_hit"], d), _p(out["near_miss"], d), _p(out["boundary"], ctypes.c_int32),
+                    _p(th, ctypes.c_int32))
+    out["threads"] = int(th[0])
+    return out
+
+
+def closest_points(points, verts, tris):
+    """Nearest point on the mesh to each query point (exact point-triangle distance, brute force)."""
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+    v0, v1, v2 = triangle_vertices(verts, tris)
+    n = pts.shape[0]
+    dist = np.empty(n)
+    pt = np.empty((n, 3))
+    ids = np.empty(n, dtype=np.int64)
+    d = ctypes.c_double
+    _load().oracle_closest_point(n, _p(pts, d), v0.shape[0], _p(v0, d), _p(v1, d), _p(v2, d), _p(dist, d),
+                                 _p(pt, d), _p(ids, ctypes.c_int64))
+    return dist, pt, ids
+
+
+def quat_to_rot(q):
+    """R_WB of a quaternion (w,x,y,z), normalised first."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ], -2)
+
+
+def camera_dirs_body(h, w, hfov):
+    """Body-frame ray directions [H,W,3] = (1, -u, v) with pixel centres at +1/2."""
+    tan_half = np.tan(0.5 * hfov)
+    c = np.arange(w, dtype=np.float64)
+    r = np.arange(h, dtype=np.float64)
+    u = (2.0 * (c + 0.5) / w - 1.0) * tan_half
+    v = (1.0 - 2.0 * (r + 0.5) / h) * tan_half * h / w
+    d = np.empty((h, w, 3))
+    d[..., 0] = 1.0
+    d[..., 1] = -u[None, :]
+    d[..., 2] = v[:, None]
+    return d
+
+
+def camera_rays(state_row, h, w, hfov):
+    """Origin [3] and world directions [H,W,3] of one agent's camera at its state row."""
+    s = np.asarray(state_row, dtype=np.float64)
+    rot = quat_to_rot(s[3:7])
+    d = camera_dirs_body(h, w, hfov) @ rot.T
+    return s[0:3].copy(), d
+
+
+def mask_from(out, eps_edge=1e-5, eps_tie=1e-5):
+    """Pixels whose closest-hit id is not decided robustly (edges, near misses, ties, clip planes)."""
+    t = out["t"]
+    scale = np.maximum(1.0, np.where(np.isfinite(t), t, 1.0))
+    both = np.isfinite(out["t2"]) & np.isfinite(t)
+    gap = np.full(t.shape, np.inf)
+    gap[both] = (out["t2"][both] - t[both]) / np.maximum(t[both], 1e-300)
+    return ((out["edge_hit"] < eps_edge * scale) | (out["near_miss"] < eps_edge * scale) | (gap < eps_tie)
+            | (out["boundary"] != 0))
+
+
+def render_view(state_row, scene, h=64, w=64, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None,
+                eps_edge=1e-5, eps_tie=1e-5, with_mask=True, pixels=None):
+    """Depth [H,W] (or [P] for a pixel subset), triangle id, planar RGB and the comparison mask.
+
+    pixels: optional int array of flat pixel indices (row * W + col) to render only those.
+    """
+    miss_depth = far if miss_depth is None else miss_depth
+    o, d = camera_rays(state_row, h, w, hfov)
+    d = d.reshape(-1, 3)
+    if pixels is not None:
+        d = d[np.asarray(pixels)]
+    out = cast(o, d, scene["verts"], scene["tris"], near, far, with_mask=with_mask)
+    hit = out["id"] >= 0
+    depth = np.where(hit, out["t"], miss_depth)
+    rgb = np.zeros((3, d.shape[0]), dtype=np.uint8)
+    if "rgb" in scene and scene["rgb"] is not None:
+        rgb[:, hit] = np.asarray(scene["rgb"])[out["id"][hit]].T
+    res = {"depth": depth, "id": out["id"].astype(np.int64), "rgb": rgb, "threads": out["threads"]}
+    if with_mask:
+        res["mask"] = mask_from(out, eps_edge, eps_tie)
+        res["raw"] = out
+    if pixels is None:
+        res["depth"] = res["depth"].reshape(h, w)
+        res["id"] = res["id"].reshape(h, w)
+        res["rgb"] = res["rgb"].reshape(3, h, w)
+        if with_mask:
+            res["mask"] = res["mask"].reshape(h, w)
+    return res

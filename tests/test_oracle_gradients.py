@@ -1,0 +1,111 @@
+"""Pins of the oracle's finite-difference gradients and nearest-point query against closed forms."""
+import math
+
+import numpy as np
+
+from oracle import dynamics as dyn
+from oracle import gradients as grd
+from oracle import render as ren
+from workloads import default_params, scenes
+from workloads.agents import make_states
+
+
+def test_central_difference_is_exact_on_quadratics():
+    a = np.array([[2.0, 0.5], [0.5, 1.0]])
+    f = lambda x: 0.5 * x @ a @ x + x.sum()
+    x = np.array([0.3, -1.2])
+    for u in (np.array([1.0, 0.0]), np.array([0.6, 0.8])):
+        assert math.isclose(grd.central_difference(f, x, u), (a @ x + 1) @ u, rel_tol=1e-8)
+
+
+def test_step_jacobian_free_fall():
+    """Free fall, no drag: dp'/dp = I, dp'/dv = dt I, dv'/dv = I (RK4 exact on this ODE)."""
+    p = default_params(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0))
+    s = make_states([[0.0, 0.0, 5.0]], p, vel=[[1.0, -2.0, 0.5]], rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    js, ja = grd.step_jacobian(s, np.zeros((1, 4)), p)
+    assert np.allclose(js[0, 0:3, 0:3], np.eye(3), atol=1e-8)
+    assert np.allclose(js[0, 0:3, 7:10], p["dt"] * np.eye(3), atol=1e-8)
+    assert np.allclose(js[0, 7:10, 7:10], np.eye(3), atol=1e-8)
+    assert np.allclose(js[0, 0:3, 3:7], 0.0, atol=1e-8)
+
+
+def test_step_jacobian_linear_drag_velocity_block():
+    """Isotropic linear drag: dv'/dv = P(-k dt / m) I with P the RK4 Taylor polynomial."""
+    k = 0.1
+    p = default_params(ctrl=dyn.SRT, k_lin=(k, k, k))
+    s = make_states([[0.0, 0.0, 5.0]], p, vel=[[1.0, -2.0, 0.5]], rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    js, _ = grd.step_jacobian(s, np.zeros((1, 4)), p)
+    z = -k * p["dt"] / p["mass"]
+    amp = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    assert np.allclose(js[0, 7:10, 7:10], amp * np.eye(3), atol=1e-8)
+
+
+def test_depth_gradient_over_floor_closed_form():
+    """Camera at height h pitched down by phi over z = 0: t = h / (sin phi - v cos phi) for the pixel ray."""
+    floor = scenes.floor_quad(half=200.0)
+    phi, h = 0.6, 2.0
+    view = {"H": 8, "W": 8, "hfov": math.radians(90), "near": 0.01, "far": 100.0}
+    s = np.zeros(17)
+    s[0:3] = [0.4, -0.3, h]
+    s[3:7] = [math.cos(phi / 2), 0.0, math.sin(phi / 2), 0.0]
+    pixels = np.array([5 * 8 + 2, 7 * 8 + 6, 4 * 8 + 4])
+    g = grd.depth_pose_gradient(s, floor, view, pixels)
+    th = math.tan(view["hfov"] / 2)
+    dq = 0.5 * np.array([-math.sin(phi / 2), 0.0, math.cos(phi / 2), 0.0])
+    for k, pix in enumerate(pixels):
+        r = pix // 8
+        v = (1 - 2 * (r + 0.5) / 8) * th
+        den = math.sin(phi) - v * math.cos(phi)
+        assert abs(g[k, 0]) < 1e-7 and abs(g[k, 1]) < 1e-7
+        assert math.isclose(g[k, 2], 1.0 / den, rel_tol=1e-7)
+        assert math.isclose(g[k, 3:7] @ dq, -h * (math.cos(phi) + v * math.sin(phi)) / den ** 2, rel_tol=1e-6)
+        # depth is invariant to the scale of q (the camera uses the normalised quaternion)
+        assert abs(g[k, 3:7] @ s[3:7]) < 1e-6
+
+
+def test_rollout_goal_term_gradient_closed_form():
+    """With nothing in view the loss is the goal term only: dL/dp0 . u = sum_k 2 w (p_k - g) . u in free fall."""
+    p = default_params(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0))
+    far_tri = scenes.plane_quad([-50.0, 0.0, 0.0], [0.0, 0.1, 0.0], [0.0, 0.0, 0.1])   # behind the camera
+    view = {"H": 4, "W": 4, "hfov": math.radians(90), "near": 0.01, "far": 100.0}
+    s0 = make_states([[0.0, 0.0, 5.0]], p, vel=[[1.0, 0.0, 0.0]], rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    acts = np.zeros((5, 1, 4))
+    goal = np.array([[3.0, 1.0, 4.0]])
+    u_s = np.zeros_like(s0)
+    u_s[0, 0:3] = [0.6, 0.0, 0.8]
+    d, stable = grd.rollout_directional(s0, acts, p, far_tri, goal, view, u_s, np.zeros_like(acts))
+    assert stable
+    traj = dyn.rollout(s0, acts, p)
+    expect = sum(2 * 0.01 * (traj[k, 0, 0:3] - goal[0]) @ u_s[0, 0:3] for k in range(1, 6))
+    assert math.isclose(d, expect, rel_tol=1e-6)
+
+
+def test_closest_point_closed_forms():
+    """Nearest-obstacle distance (Sec. III-B spatial distance module): plane, edge and corner regions of a box."""
+    v, t = scenes.boxes_mesh(np.array([[0.0, 0.0, 0.0]]), np.array([[2.0, 1.0, 3.0]]))
+    pts = np.array([[1.0, 0.5, 4.0],      # above the top face: distance 1
+                    [3.0, 2.0, 1.5],      # beside the vertical edge x=2,y=1: distance sqrt(2)
+                    [-1.0, -1.0, -1.0],   # corner (0,0,0): sqrt(3)
+                    [1.0, 0.5, 1.5]])     # inside: distance to the nearest face (y=0 or y=1): 0.5
+    dist, pt, ids = ren.closest_points(pts, v, t)
+    assert np.allclose(dist, [1.0, math.sqrt(2), math.sqrt(3), 0.5], atol=1e-14)
+    assert np.allclose(pt[0], [1.0, 0.5, 3.0]) and np.allclose(pt[2], [0.0, 0.0, 0.0])
+    assert np.all(ids >= 0)
+
+
+def test_golden_box_room_regression():
+    """The oracle reproduces its committed box-room fixture (guards against silent oracle edits)."""
+    import json
+    import os
+    from oracle import render as ren2
+    from workloads import agents, scenes as sc_mod
+    with open(os.path.join(os.path.dirname(__file__), "golden", "box_room_oracle.json")) as f:
+        gold = json.load(f)
+    p = default_params()
+    traj = dyn.rollout(agents.box_room_start(p), agents.random_actions(2, 100, 1, p), p)
+    for k, row in gold["states"].items():
+        assert np.allclose(traj[int(k), 0], row, rtol=0, atol=1e-12)
+    r = ren2.render_view(traj[100, 0], sc_mod.box_room(seed=1), 64, 64, math.pi / 2,
+                         pixels=np.array(gold["pixels"]))
+    assert np.allclose(r["depth"], gold["depth"], rtol=1e-13)
+    assert r["id"].tolist() == gold["id"]

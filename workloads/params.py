@@ -1,0 +1,51 @@
+"""Quadrotor and integrator configuration values used by every workload.
+
+The airframe numbers (mass 1.0 kg, arm 0.15 m, inertia diag(0.0025, 0.0025,
+0.0045) kg m^2, rotor time constant 0.03 s, linear drag 0.1 N s/m, control step
+0.02 s) are the benchmark configuration.  The constants the paper leaves open
+(Sec. III-A, Eqs. 2-4 and the controller paragraph) take these readings:
+yaw reaction ratio 0.016 m, per-rotor thrust limit 0.75 m g (thrust-to-weight 3),
+body-rate gains diag(20, 20, 10) 1/s, gravity 9.81 m/s^2 along -z, no quadratic
+drag term, one sub-step per control step, RK4 integration, CTBR control.
+
+Values are plain Python floats; callers cast them to float32 for the device.
+"""
+
+# Field order of the parameter block (mirrors the C struct ``vf_dyn_params``).
+PARAM_FIELDS = (
+    "dt", "n_sub", "integrator", "ctrl",
+    "mass", "arm", "J", "tau_motor", "kappa_yaw", "f_max",
+    "k_lin", "c_quad", "g", "k_rate",
+)
+
+INTEGRATOR_RK4 = 0
+INTEGRATOR_EULER = 1
+CTRL_CTBR = 0
+CTRL_SRT = 1
+
+
+def default_params(**overrides):
+    """Return the benchmark airframe/integrator configuration as a dict."""
+    g = 9.81
+    mass = 1.0
+    p = {
+        "dt": 0.02,
+        "n_sub": 1,
+        "integrator": INTEGRATOR_RK4,
+        "ctrl": CTRL_CTBR,
+        "mass": mass,
+        "arm": 0.15,
+        "J": (0.0025, 0.0025, 0.0045),
+        "tau_motor": 0.03,
+        "kappa_yaw": 0.016,
+        "f_max": 0.75 * mass * g,
+        "k_lin": (0.1, 0.1, 0.1),
+        "c_quad": (0.0, 0.0, 0.0),
+        "g": g,
+        "k_rate": (20.0, 20.0, 10.0),
+    }
+    for k, v in overrides.items():
+        if k not in p:
+            raise KeyError(f"unknown parameter {k!r}")
+        p[k] = v
+    return p
