@@ -1,0 +1,632 @@
+// Device BVH build for a triangle scene (Sec. III-B scenes; the paper rasterises,
+// this path ray casts, so the scene needs an acceleration structure).
+//
+// Pipeline (all on the caller's stream, one scene at a time):
+//   1. tri_prep      per-triangle bounds and centroid, block partial bounds
+//   2. reduce        centroid and scene bounds
+//   3. morton        30-bit Morton code of the quantised centroid, value = index
+//   4. radix sort    stable LSD, 8-bit digits, 4 passes (histogram / scan / scatter)
+//   5. radix tree    binary radix tree over the sorted codes (Karras, HPG 2012),
+//                    duplicate codes split by index
+//   6. collapse      level by level: each 4-wide node takes the two children of its
+//                    binary node and repeatedly opens the child with the most
+//                    triangles until it has four; children with <= kLeafMax
+//                    triangles become leaves (a contiguous sorted range)
+//   7. bounds        bottom-up per level (deepest first), leaf boxes padded by a
+//                    few ulps, plus per-octant near-to-far child orders
+//   8. triangles     (v0, e1, e2, caller id) in sorted order, id -> position map
+// Node indices are assigned by prefix sums, so a rebuild of the same input is
+// bitwise identical.
+#include <float.h>
+
+#include "vf_internal.h"
+
+namespace vf {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per block
+constexpr int kPrepThreads = 256;
+
+__device__ __forceinline__ uint32_t expand_bits10(uint32_t v) {
+    v = (v * 0x00010001u) & 0xFF0000FFu;
+    v = (v * 0x00000101u) & 0x0F00F00Fu;
+    v = (v * 0x00000011u) & 0xC30C30C3u;
+    v = (v * 0x00000005u) & 0x49249249u;
+    return v;
+}
+
+__global__ void k_tri_prep(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris, int32_t nt,
+                           float4* __restrict__ tlo, float4* __restrict__ thi, float4* __restrict__ cen,
+                           float* __restrict__ partial, uint32_t* __restrict__ err) {
+    __shared__ float red[6][kPrepThreads];
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    float clo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, chi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    if (t < nt) {
+        int32_t ia = tris[3 * t], ib = tris[3 * t + 1], ic = tris[3 * t + 2];
+        bool ok = ia >= 0 && ib >= 0 && ic >= 0 && ia < nv && ib < nv && ic < nv;
+        if (!ok) {
+            atomicOr(err, kErrTriIndex);
+            ia = ib = ic = 0;
+        }
+        float a[3], b[3], c[3], lo[3], hi[3], ce[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = verts[3 * (int64_t)ia + k];
+            b[k] = verts[3 * (int64_t)ib + k];
+            c[k] = verts[3 * (int64_t)ic + k];
+            lo[k] = fminf(a[k], fminf(b[k], c[k]));
+            hi[k] = fmaxf(a[k], fmaxf(b[k], c[k]));
+            ce[k] = 0.5f * lo[k] + 0.5f * hi[k];   // box centre: robust for degenerate triangles
+            clo[k] = ce[k];
+            chi[k] = ce[k];
+        }
+        tlo[t] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        thi[t] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        cen[t] = make_float4(ce[0], ce[1], ce[2], 0.f);
+    }
+    for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = clo[k];
+        red[3 + k][threadIdx.x] = chi[k];
+    }
+    __syncthreads();
+    for (int s = kPrepThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int k = 0; k < 3; ++k) {
+                red[k][threadIdx.x] = fminf(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+                red[3 + k][threadIdx.x] = fmaxf(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Single block: reduce block partials (centroid bounds) and the triangle boxes (scene bounds).
+__global__ void k_reduce_bounds(const float* __restrict__ partial, int nblocks, const float4* __restrict__ tlo,
+                                const float4* __restrict__ thi, int32_t nt, float* __restrict__ out /*12*/) {
+    __shared__ float red[12][kScanThreads];
+    float v[12];
+    for (int k = 0; k < 3; ++k) { v[k] = FLT_MAX; v[3 + k] = -FLT_MAX; v[6 + k] = FLT_MAX; v[9 + k] = -FLT_MAX; }
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 3; ++k) {
+            v[k] = fminf(v[k], partial[6 * b + k]);
+            v[3 + k] = fmaxf(v[3 + k], partial[6 * b + 3 + k]);
+        }
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        float4 lo = tlo[t], hi = thi[t];
+        v[6] = fminf(v[6], lo.x); v[7] = fminf(v[7], lo.y); v[8] = fminf(v[8], lo.z);
+        v[9] = fmaxf(v[9], hi.x); v[10] = fmaxf(v[10], hi.y); v[11] = fmaxf(v[11], hi.z);
+    }
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = kScanThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 12; ++k) {
+                bool is_min = (k < 3) || (k >= 6 && k < 9);
+                float a = red[k][threadIdx.x], b = red[k][threadIdx.x + s];
+                red[k][threadIdx.x] = is_min ? fminf(a, b) : fmaxf(a, b);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_morton(const float4* __restrict__ cen, int32_t nt, const float* __restrict__ bounds,
+                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    float4 c = cen[t];
+    float lo[3] = {bounds[0], bounds[1], bounds[2]};
+    float ext[3] = {bounds[3] - lo[0], bounds[4] - lo[1], bounds[5] - lo[2]};
+    float cc[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+        float u = ext[k] > 0.f ? (cc[k] - lo[k]) / ext[k] : 0.f;
+        u = fminf(fmaxf(u * 1024.0f, 0.0f), 1023.0f);
+        q[k] = (uint32_t)u;
+    }
+    keys[t] = (expand_bits10(q[0]) << 2) | (expand_bits10(q[1]) << 1) | expand_bits10(q[2]);
+    vals[t] = (uint32_t)t;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (single workgroup; used for the sort histograms and the collapse)
+// ---------------------------------------------------------------------------
+__global__ void k_scan_exclusive(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
+                                 uint32_t* __restrict__ total) {
+    __shared__ uint32_t sums[kScanThreads];
+    int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
+    int64_t b = threadIdx.x * chunk, e = b + chunk < n ? b + chunk : n;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += in[i];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the chunk sums
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint32_t v = (int)threadIdx.x >= off ? sums[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sums[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x > 0 ? sums[threadIdx.x - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == kScanThreads - 1 && total) *total = sums[kScanThreads - 1];
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, value) pairs, 8-bit digits
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t* __restrict__ keys, int32_t n, int shift,
+                                                            uint32_t* __restrict__ hist, int nblocks) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t e = base + j * kSortThreads + threadIdx.x;
+        if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Each wave owns 512 consecutive keys of the block's tile (8 rows of 64) so the
+// in-tile order is (wave, row, lane); ranks among equal digits follow that order.
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                               int32_t n, int shift,
+                                                               const uint32_t* __restrict__ offsets, int nblocks) {
+    __shared__ uint32_t wrun[kSortThreads / kWave][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = lane; d < 256; d += 64) wrun[wave][d] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t wbase = (int64_t)blockIdx.x * kSortTile + wave * (kSortItems * kWave);
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    for (int j = 0; j < kSortItems; ++j) {
+        int64_t e = wbase + j * kWave + lane;
+        bool valid = e < n;
+        key[j] = valid ? kin[e] : 0u;
+        val[j] = valid ? vin[e] : 0u;
+        uint32_t dig = (key[j] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dig >> b) & 1u;
+            uint64_t m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t before = wrun[wave][dig];
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        // the highest lane of each peer group advances the running count
+        bool leader = valid && ((peers >> lane) >> 1) == 0ull;
+        __builtin_amdgcn_wave_barrier();
+        if (leader) wrun[wave][dig] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        if (!valid) rank[j] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // exclusive prefix over waves, per digit
+    {
+        int d = threadIdx.x;
+        uint32_t s = 0;
+        for (int w = 0; w < kSortThreads / kWave; ++w) {
+            uint32_t c = wrun[w][d];
+            wrun[w][d] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < kSortItems; ++j) {
+        if (rank[j] == 0xFFFFFFFFu) continue;
+        uint32_t dig = (key[j] >> shift) & 255u;
+        uint32_t pos = offsets[(int64_t)dig * nblocks + blockIdx.x] + wrun[wave][dig] + rank[j];
+        kout[pos] = key[j];
+        vout[pos] = val[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binary radix tree (Karras 2012): internal node i covers [first, last]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int common_prefix(const uint32_t* __restrict__ k, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    uint32_t a = k[i], b = k[j];
+    if (a == b) return 32 + __clz((uint32_t)(i ^ j));
+    return __clz(a ^ b);
+}
+
+__global__ void k_radix_tree(const uint32_t* __restrict__ k, int32_t n, int32_t* __restrict__ left,
+                             int32_t* __restrict__ right, int32_t* __restrict__ first, int32_t* __restrict__ last) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (common_prefix(k, n, i, i + 1) - common_prefix(k, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = common_prefix(k, n, i, i - d);
+    int lmax = 2;
+    while (common_prefix(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (common_prefix(k, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = common_prefix(k, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (common_prefix(k, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int gamma = i + s * d + (d < 0 ? -1 : 0);
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    left[i] = (lo == gamma) ? -(gamma + 1) : gamma;
+    right[i] = (hi == gamma + 1) ? -(gamma + 2) : gamma + 1;
+    first[i] = lo;
+    last[i] = hi;
+}
+
+// ---------------------------------------------------------------------------
+// collapse to 4-wide nodes, one level per launch
+// ---------------------------------------------------------------------------
+struct TreeView {
+    const int32_t* left;
+    const int32_t* right;
+    const int32_t* first;
+    const int32_t* last;
+    __device__ int count(int32_t r) const { return r >= 0 ? last[r] - first[r] + 1 : 1; }
+    __device__ int start(int32_t r) const { return r >= 0 ? first[r] : -r - 1; }
+};
+
+constexpr int32_t kEmpty = INT32_MIN;
+
+__global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entries, int32_t level_base, int32_t n_level,
+                                 int32_t* __restrict__ kids, uint32_t* __restrict__ n_inner) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_level) return;
+    int32_t r = entries[level_base + e];
+    int32_t c[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+    int nk;
+    if (r == kEmpty) {  // whole scene in one leaf (handled by the host; kept for safety)
+        nk = 0;
+    } else {
+        c[0] = tv.left[r];
+        c[1] = tv.right[r];
+        nk = 2;
+        while (nk < 4) {
+            int best = -1, bestc = kLeafMax;
+            for (int k = 0; k < nk; ++k) {
+                if (c[k] >= 0) {
+                    int cc = tv.count(c[k]);
+                    if (cc > bestc) { bestc = cc; best = k; }
+                }
+            }
+            if (best < 0) break;
+            int32_t rr = c[best];
+            c[best] = tv.left[rr];
+            c[nk++] = tv.right[rr];
+        }
+    }
+    uint32_t ni = 0;
+    for (int k = 0; k < 4; ++k) {
+        kids[4 * (int64_t)e + k] = c[k];
+        if (c[k] != kEmpty && c[k] >= 0 && tv.count(c[k]) > kLeafMax) ++ni;
+    }
+    n_inner[e] = ni;
+}
+
+__global__ void k_collapse_emit(TreeView tv, int32_t* __restrict__ entries, int32_t level_base, int32_t n_level,
+                                const int32_t* __restrict__ kids, const uint32_t* __restrict__ prefix,
+                                int32_t next_base, Node4* __restrict__ nodes) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_level) return;
+    Node4& nd = nodes[level_base + e];
+    uint32_t at = prefix[e];
+    for (int k = 0; k < 4; ++k) {
+        int32_t c = kids[4 * (int64_t)e + k];
+        if (c == kEmpty) {
+            nd.child[k] = -1;
+            nd.count[k] = 0;
+        } else if (c >= 0 && tv.count(c) > kLeafMax) {
+            int32_t idx = next_base + (int32_t)at;
+            entries[idx] = c;
+            nd.child[k] = idx;
+            nd.count[k] = 0;
+            ++at;
+        } else {
+            nd.child[k] = -(tv.start(c) + 1);
+            nd.count[k] = (uint8_t)tv.count(c);
+        }
+    }
+    nd.pad = 0;
+}
+
+__device__ __forceinline__ float pad_down(float x) { return x - (fabsf(x) + 1.0f) * 1.9073486e-6f; }  // 2^-19
+__device__ __forceinline__ float pad_up(float x) { return x + (fabsf(x) + 1.0f) * 1.9073486e-6f; }
+
+__global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t n_level,
+                         const uint32_t* __restrict__ sorted_vals, const float4* __restrict__ tlo,
+                         const float4* __restrict__ thi) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_level) return;
+    Node4& nd = nodes[level_base + e];
+    float lo[4][3], hi[4][3];
+    bool valid[4];
+    for (int k = 0; k < 4; ++k) {
+        int32_t c = nd.child[k];
+        int cnt = nd.count[k];
+        float l[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, h[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+        valid[k] = c >= 0 || cnt > 0;
+        if (c >= 0) {
+            const Node4& ch = nodes[c];
+            for (int j = 0; j < 4; ++j) {
+                if (ch.child[j] < 0 && ch.count[j] == 0) continue;
+                l[0] = fminf(l[0], ch.lo_x[j]); h[0] = fmaxf(h[0], ch.hi_x[j]);
+                l[1] = fminf(l[1], ch.lo_y[j]); h[1] = fmaxf(h[1], ch.hi_y[j]);
+                l[2] = fminf(l[2], ch.lo_z[j]); h[2] = fmaxf(h[2], ch.hi_z[j]);
+            }
+        } else if (cnt > 0) {
+            int f = -c - 1;
+            for (int j = 0; j < cnt; ++j) {
+                uint32_t t = sorted_vals[f + j];
+                float4 a = tlo[t], b = thi[t];
+                l[0] = fminf(l[0], a.x); l[1] = fminf(l[1], a.y); l[2] = fminf(l[2], a.z);
+                h[0] = fmaxf(h[0], b.x); h[1] = fmaxf(h[1], b.y); h[2] = fmaxf(h[2], b.z);
+            }
+            for (int a = 0; a < 3; ++a) { l[a] = pad_down(l[a]); h[a] = pad_up(h[a]); }
+        }
+        for (int a = 0; a < 3; ++a) { lo[k][a] = l[a]; hi[k][a] = h[a]; }
+    }
+    for (int k = 0; k < 4; ++k) {
+        nd.lo_x[k] = lo[k][0]; nd.hi_x[k] = hi[k][0];
+        nd.lo_y[k] = lo[k][1]; nd.hi_y[k] = hi[k][1];
+        nd.lo_z[k] = lo[k][2]; nd.hi_z[k] = hi[k][2];
+    }
+    // near-to-far child order for each ray-direction octant: sort slots by the
+    // projection of the box centre on the octant's diagonal; empty slots last
+    uint64_t orders = 0;
+    for (int o = 0; o < 8; ++o) {
+        float sx = (o & 1) ? -1.f : 1.f, sy = (o & 2) ? -1.f : 1.f, sz = (o & 4) ? -1.f : 1.f;
+        float key[4];
+        int idx[4] = {0, 1, 2, 3};
+        for (int k = 0; k < 4; ++k)
+            key[k] = valid[k] ? sx * (lo[k][0] + hi[k][0]) + sy * (lo[k][1] + hi[k][1]) + sz * (lo[k][2] + hi[k][2])
+                              : FLT_MAX;
+        for (int a = 1; a < 4; ++a)
+            for (int b = a; b > 0 && key[idx[b]] < key[idx[b - 1]]; --b) {
+                int tmp = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = tmp;
+            }
+        uint64_t byte = (uint64_t)(idx[0] | (idx[1] << 2) | (idx[2] << 4) | (idx[3] << 6));
+        orders |= byte << (8 * o);
+    }
+    nd.order_lo = (uint32_t)orders;
+    nd.order_hi = (uint32_t)(orders >> 32);
+}
+
+__global__ void k_single_leaf_root(Node4* __restrict__ nodes, int32_t nt, const float4* __restrict__ tlo,
+                                   const float4* __restrict__ thi) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Node4& nd = nodes[0];
+    float l[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, h[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int t = 0; t < nt; ++t) {
+        float4 a = tlo[t], b = thi[t];
+        l[0] = fminf(l[0], a.x); l[1] = fminf(l[1], a.y); l[2] = fminf(l[2], a.z);
+        h[0] = fmaxf(h[0], b.x); h[1] = fmaxf(h[1], b.y); h[2] = fmaxf(h[2], b.z);
+    }
+    for (int k = 0; k < 4; ++k) {
+        bool v = k == 0;
+        nd.lo_x[k] = v ? pad_down(l[0]) : FLT_MAX; nd.hi_x[k] = v ? pad_up(h[0]) : -FLT_MAX;
+        nd.lo_y[k] = v ? pad_down(l[1]) : FLT_MAX; nd.hi_y[k] = v ? pad_up(h[1]) : -FLT_MAX;
+        nd.lo_z[k] = v ? pad_down(l[2]) : FLT_MAX; nd.hi_z[k] = v ? pad_up(h[2]) : -FLT_MAX;
+        nd.child[k] = v ? -1 : -1;
+        nd.count[k] = v ? (uint8_t)nt : 0;
+    }
+    nd.order_lo = 0xE4E4E4E4u;  // identity order 0,1,2,3 for every octant
+    nd.order_hi = 0xE4E4E4E4u;
+    nd.pad = 0;
+}
+
+__global__ void k_tri_write(const float* __restrict__ verts, const int32_t* __restrict__ tris,
+                            const uint32_t* __restrict__ sorted_vals, int32_t nt, int64_t nv, Tri* __restrict__ out,
+                            int32_t* __restrict__ sorted_of) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nt) return;
+    uint32_t t = sorted_vals[j];
+    int32_t ia = tris[3 * (int64_t)t], ib = tris[3 * (int64_t)t + 1], ic = tris[3 * (int64_t)t + 2];
+    if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) ia = ib = ic = 0;
+    float a[3], b[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+        a[k] = verts[3 * (int64_t)ia + k];
+        b[k] = verts[3 * (int64_t)ib + k];
+        c[k] = verts[3 * (int64_t)ic + k];
+    }
+    Tri r;
+    r.v0x = a[0]; r.v0y = a[1]; r.v0z = a[2]; r.id = (int32_t)t;
+    r.e1x = b[0] - a[0]; r.e1y = b[1] - a[1]; r.e1z = b[2] - a[2]; r.pad1 = 0.f;
+    r.e2x = c[0] - a[0]; r.e2y = c[1] - a[1]; r.e2z = c[2] - a[2]; r.pad2 = 0.f;
+    out[j] = r;
+    sorted_of[t] = j;
+}
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+// Scratch of one build; freed when the build returns.
+struct BuildScratch {
+    vf_ctx* ctx;
+    std::vector<std::pair<void*, int64_t>> held;
+    explicit BuildScratch(vf_ctx* c) : ctx(c) {}
+    ~BuildScratch() {
+        for (auto& h : held) ctx_free(ctx, h.first, h.second);
+    }
+    template <class T>
+    vf_status get(T** p, int64_t count) {
+        void* q = nullptr;
+        int64_t bytes = count * (int64_t)sizeof(T);
+        if (bytes <= 0) bytes = 16;
+        vf_status st = ctx_alloc(ctx, &q, bytes);
+        if (st != VF_OK) return st;
+        held.emplace_back(q, bytes);
+        *p = (T*)q;
+        return VF_OK;
+    }
+};
+
+vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t* tris, int32_t nt,
+                      const uint8_t* rgb, hipStream_t st, SceneHost* out) {
+    BuildScratch sc(ctx);
+    float4 *tlo, *thi, *cen;
+    float *partial, *bounds;
+    uint32_t *keys, *vals, *keys2, *vals2, *hist, *offs, *total;
+    int32_t *left, *right, *first, *last, *entries, *kids;
+    uint32_t *n_inner, *prefix;
+    const int nb_prep = blocks_for(nt, kPrepThreads);
+    const int nb_sort = blocks_for(nt, kSortTile);
+    vf_status s;
+#define GET(p, n) if ((s = sc.get(&p, n)) != VF_OK) return s
+    GET(tlo, nt); GET(thi, nt); GET(cen, nt); GET(partial, 6 * (int64_t)nb_prep); GET(bounds, 12);
+    GET(keys, nt); GET(vals, nt); GET(keys2, nt); GET(vals2, nt);
+    GET(hist, 256 * (int64_t)nb_sort); GET(offs, 256 * (int64_t)nb_sort); GET(total, 4);
+    GET(left, nt); GET(right, nt); GET(first, nt); GET(last, nt);
+    GET(entries, nt + 1); GET(kids, 4 * (int64_t)(nt + 1)); GET(n_inner, nt + 1); GET(prefix, nt + 1);
+#undef GET
+
+    hipEvent_t ev0, ev1;
+    VF_HIP(hipEventCreate(&ev0));
+    VF_HIP(hipEventCreate(&ev1));
+    VF_HIP(hipEventRecord(ev0, st));
+
+    hipLaunchKernelGGL(k_tri_prep, dim3(nb_prep), dim3(kPrepThreads), 0, st, verts, nv, tris, nt, tlo, thi, cen,
+                       partial, ctx->d_err);
+    hipLaunchKernelGGL(k_reduce_bounds, dim3(1), dim3(kScanThreads), 0, st, partial, nb_prep, tlo, thi, nt, bounds);
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, 256)), dim3(256), 0, st, cen, nt, bounds, keys, vals);
+    uint32_t *ka = keys, *va = vals, *kb = keys2, *vb = vals2;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, nt, shift, hist, nb_sort);
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(kScanThreads), 0, st, hist, offs, 256 * (int64_t)nb_sort,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, va, kb, vb, nt, shift, offs,
+                           nb_sort);
+        uint32_t* t;
+        t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    // after 4 passes the sorted pairs are back in (keys, vals)
+
+    // scene block: nodes | tris | sorted_of | rgb
+    const int64_t max_nodes = nt > 1 ? nt : 1;
+    int64_t node_bytes = max_nodes * (int64_t)sizeof(Node4);
+    int64_t tri_bytes = (int64_t)nt * (int64_t)sizeof(Tri);
+    int64_t map_bytes = ((int64_t)nt * 4 + 255) / 256 * 256;
+    int64_t rgb_bytes = ((int64_t)nt * 3 + 255) / 256 * 256;
+    Node4* nodes = nullptr;
+    // allocate the final block after the topology is known (node count); use a
+    // temporary node array of the upper-bound size first
+    Node4* tmp_nodes;
+    if ((s = sc.get(&tmp_nodes, max_nodes)) != VF_OK) return s;
+
+    std::vector<int32_t> level_base, level_n;
+    int depth = 0;
+    int32_t n_nodes = 0;
+    bool single_leaf = nt <= kLeafMax;
+    if (single_leaf) {
+        hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(64), 0, st, tmp_nodes, nt, tlo, thi);
+        n_nodes = 1;
+        depth = 1;
+    } else {
+        hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, ka, nt, left, right, first,
+                           last);
+        TreeView tv{left, right, first, last};
+        int32_t root = 0;
+        VF_HIP(hipMemcpyAsync(entries, &root, sizeof(int32_t), hipMemcpyHostToDevice, st));
+        int32_t base = 0, n_level = 1;
+        while (n_level > 0) {
+            if (depth >= kMaxBvhDepth) return fail(VF_EINVAL, "scene BVH deeper than the traversal stack allows");
+            level_base.push_back(base);
+            level_n.push_back(n_level);
+            ++depth;
+            hipLaunchKernelGGL(k_collapse_count, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries, base,
+                               n_level, kids, n_inner);
+            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(kScanThreads), 0, st, n_inner, prefix,
+                               (int64_t)n_level, total);
+            int32_t next_base = base + n_level;
+            hipLaunchKernelGGL(k_collapse_emit, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries, base,
+                               n_level, kids, prefix, next_base, tmp_nodes);
+            uint32_t nnext = 0;
+            VF_HIP(hipMemcpyAsync(&nnext, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            VF_HIP(hipStreamSynchronize(st));
+            base = next_base;
+            n_level = (int32_t)nnext;
+        }
+        n_nodes = base;
+        for (int L = depth - 1; L >= 0; --L)
+            hipLaunchKernelGGL(k_bounds, dim3(blocks_for(level_n[L], 128)), dim3(128), 0, st, tmp_nodes,
+                               level_base[L], level_n[L], va == vals ? vals : va, tlo, thi);
+    }
+    node_bytes = (int64_t)n_nodes * (int64_t)sizeof(Node4);
+    int64_t total_bytes = node_bytes + tri_bytes + map_bytes + rgb_bytes;
+    void* block = nullptr;
+    if ((s = ctx_alloc(ctx, &block, total_bytes)) != VF_OK) return s;
+    nodes = (Node4*)block;
+    Tri* tri_out = (Tri*)((char*)block + node_bytes);
+    int32_t* sorted_of = (int32_t*)((char*)block + node_bytes + tri_bytes);
+    uint8_t* rgb_out = (uint8_t*)((char*)block + node_bytes + tri_bytes + map_bytes);
+    hipError_t e = hipMemcpyAsync(nodes, tmp_nodes, node_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_tri_write, dim3(blocks_for(nt, 256)), dim3(256), 0, st, verts, tris, va, nt, nv, tri_out,
+                           sorted_of);
+        if (rgb)
+            e = hipMemcpyAsync(rgb_out, rgb, (size_t)nt * 3, hipMemcpyDeviceToDevice, st);
+        else
+            hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for((int64_t)nt * 3, 256)), dim3(256), 0, st, rgb_out,
+                               (int64_t)nt * 3, (uint8_t)128);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev1, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        ctx_free(ctx, block, total_bytes);
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        return hip_fail(e, "scene build");
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    float bnd[12];
+    VF_HIP(hipMemcpy(bnd, bounds, sizeof(bnd), hipMemcpyDeviceToHost));
+
+    out->block = block;
+    out->bytes = total_bytes;
+    out->info.n_tris = nt;
+    out->info.n_nodes = n_nodes;
+    out->info.n_leaves = 0;
+    out->info.bytes = total_bytes;
+    out->info.depth = depth;
+    out->info.leaf_max = kLeafMax;
+    for (int k = 0; k < 3; ++k) {
+        out->info.bounds_lo[k] = bnd[6 + k];
+        out->info.bounds_hi[k] = bnd[9 + k];
+    }
+    out->info.build_ms = ms;
+    out->desc.nodes = nodes;
+    out->desc.tris = tri_out;
+    out->desc.rgb = rgb_out;
+    out->desc.sorted_of = sorted_of;
+    out->desc.n_tris = nt;
+    out->desc.root_leaf = single_leaf ? 1 : 0;
+    out->desc.valid = 1;
+    return VF_OK;
+}
+
+}  // namespace vf

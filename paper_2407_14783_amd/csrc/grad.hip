@@ -1,0 +1,379 @@
+// Adjoint kernels for the differentiable forms (Sec. III-A: differentiable
+// dynamics whose analytic gradients drive learning).
+//
+// k_step_backward: reverse mode of one control step, written out by hand.  The
+// forward sub-steps are recomputed from the saved state (for sub-step j the
+// forward runs j sub-steps from the start, so n_sub sub-steps cost n_sub(n_sub+1)/2
+// forward sub-steps; n_sub is small).  Within a sub-step the RK4 stages are
+// recomputed and walked backwards: normalisation, the RK4 combination, the four
+// stage derivatives (Eq. 1 with Eq. 2 drag and Eq. 3 wrench), the closed-form
+// rotor lag (Eq. 4), the square root, the clamp (zero gradient when clamped)
+// and the CTBR mixer / rate controller.
+//
+// k_render_backward: depth t = n.(V0 - o) / n.d on the hit triangle's plane;
+// dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B.  Per agent the pixel
+// sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix) are reduced in
+// a fixed order, then chained through R and the quaternion normalisation.
+#include "dynamics.h"
+#include "vf_internal.h"
+
+namespace vf {
+
+// d/dq of sum_ij G_ij R_ij(q) for a unit quaternion q (no normalisation term).
+__device__ __forceinline__ void rot_vjp(const float q[4], const float G[9], float out[4]) {
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    out[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    out[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] - 2.f * x * G[8]);
+    out[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - 2.f * y * G[8]);
+    out[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
+}
+
+// lambda_q of q -> q/|q| given lambda on the normalised value.
+__device__ __forceinline__ void normalize_vjp(const float q[4], const float lam_n[4], float lam_q[4]) {
+    float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    float inv = 1.0f / n;
+    float qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
+    float dot = qn[0] * lam_n[0] + qn[1] * lam_n[1] + qn[2] * lam_n[2] + qn[3] * lam_n[3];
+    for (int i = 0; i < 4; ++i) lam_q[i] = (lam_n[i] - qn[i] * dot) * inv;
+}
+
+// VJP of c(om) = om x (J om): returns d/d om of lam . c.
+__device__ __forceinline__ void gyro_vjp(const DynConst& c, const float om[3], const float lam[3], float out[3]) {
+    float j[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
+    // j x lam
+    float a0 = j[1] * lam[2] - j[2] * lam[1];
+    float a1 = j[2] * lam[0] - j[0] * lam[2];
+    float a2 = j[0] * lam[1] - j[1] * lam[0];
+    // J (lam x om)
+    float b0 = c.J[0] * (lam[1] * om[2] - lam[2] * om[1]);
+    float b1 = c.J[1] * (lam[2] * om[0] - lam[0] * om[2]);
+    float b2 = c.J[2] * (lam[0] * om[1] - lam[1] * om[0]);
+    out[0] = a0 + b0;
+    out[1] = a1 + b1;
+    out[2] = a2 + b2;
+}
+
+// Reverse of derivative(): given the cotangent L of d = F(y, w), accumulate into ly, lw.
+__device__ __forceinline__ void derivative_vjp(const DynConst& c, const Vec13& y, const float w[4], const Vec13& L,
+                                               Vec13& ly, float lw[4]) {
+    float f[4] = {w[0] * w[0], w[1] * w[1], w[2] * w[2], w[3] * w[3]};
+    float fz, tau[3];
+    rotor_wrench(c, f, fz, tau);
+    float r[9];
+    quat_rot(y.q, r);
+    float vb[3];
+    for (int i = 0; i < 3; ++i) vb[i] = r[0 + i] * y.v[0] + r[3 + i] * y.v[1] + r[6 + i] * y.v[2];
+    float fb[3];
+    for (int i = 0; i < 3; ++i) fb[i] = -c.k_lin[i] * vb[i] - c.c_quad[i] * fabsf(vb[i]) * vb[i];
+    fb[2] += fz;
+    // d.p = v
+    for (int i = 0; i < 3; ++i) ly.v[i] += L.p[i];
+    // d.v = R fb / m - g z
+    float lv[3] = {L.v[0] * c.inv_mass, L.v[1] * c.inv_mass, L.v[2] * c.inv_mass};
+    float G[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[3 * i + j] = lv[i] * fb[j];
+    float lfb[3];
+    for (int j = 0; j < 3; ++j) lfb[j] = r[j] * lv[0] + r[3 + j] * lv[1] + r[6 + j] * lv[2];
+    float lfz = lfb[2];
+    float lvb[3];
+    for (int i = 0; i < 3; ++i) lvb[i] = lfb[i] * (-c.k_lin[i] - 2.0f * c.c_quad[i] * fabsf(vb[i]));
+    // vb_i = sum_j R_ji v_j
+    for (int j = 0; j < 3; ++j) ly.v[j] += r[3 * j + 0] * lvb[0] + r[3 * j + 1] * lvb[1] + r[3 * j + 2] * lvb[2];
+    for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i) G[3 * j + i] += y.v[j] * lvb[i];
+    // R = R(q/|q|)
+    {
+        float n = sqrtf(y.q[0] * y.q[0] + y.q[1] * y.q[1] + y.q[2] * y.q[2] + y.q[3] * y.q[3]);
+        float inv = 1.0f / n;
+        float qn[4] = {y.q[0] * inv, y.q[1] * inv, y.q[2] * inv, y.q[3] * inv};
+        float lqn[4], lq[4];
+        rot_vjp(qn, G, lqn);
+        normalize_vjp(y.q, lqn, lq);
+        for (int i = 0; i < 4; ++i) ly.q[i] += lq[i];
+    }
+    // d.q = 1/2 q (x) (0, om)
+    {
+        const float* q = y.q;
+        const float* om = y.w;
+        float a = 0.5f * L.q[0], b = 0.5f * L.q[1], cc = 0.5f * L.q[2], d = 0.5f * L.q[3];
+        ly.q[0] += b * om[0] + cc * om[1] + d * om[2];
+        ly.q[1] += -a * om[0] - cc * om[2] + d * om[1];
+        ly.q[2] += -a * om[1] + b * om[2] - d * om[0];
+        ly.q[3] += -a * om[2] - b * om[1] + cc * om[0];
+        ly.w[0] += -a * q[1] + b * q[0] + cc * q[3] - d * q[2];
+        ly.w[1] += -a * q[2] - b * q[3] + cc * q[0] + d * q[1];
+        ly.w[2] += -a * q[3] + b * q[2] - cc * q[1] + d * q[0];
+    }
+    // d.w = J^-1 (tau - om x J om)
+    float ltau[3] = {L.w[0] * c.inv_J[0], L.w[1] * c.inv_J[1], L.w[2] * c.inv_J[2]};
+    {
+        float lc[3] = {-ltau[0], -ltau[1], -ltau[2]};
+        float g[3];
+        gyro_vjp(c, y.w, lc, g);
+        for (int i = 0; i < 3; ++i) ly.w[i] += g[i];
+    }
+    // tau, fz from f
+    float a = c.arm_a, k = c.kappa;
+    float lf[4];
+    lf[0] = lfz - a * ltau[0] - a * ltau[1] + k * ltau[2];
+    lf[1] = lfz + a * ltau[0] + a * ltau[1] + k * ltau[2];
+    lf[2] = lfz + a * ltau[0] - a * ltau[1] - k * ltau[2];
+    lf[3] = lfz - a * ltau[0] + a * ltau[1] - k * ltau[2];
+    for (int i = 0; i < 4; ++i) lw[i] += 2.0f * w[i] * lf[i];
+}
+
+__device__ __forceinline__ void zero13(Vec13& v) {
+    for (int i = 0; i < 3; ++i) { v.p[i] = 0.f; v.v[i] = 0.f; v.w[i] = 0.f; }
+    for (int i = 0; i < 4; ++i) v.q[i] = 0.f;
+}
+
+__device__ __forceinline__ void load13(Vec13& y, const float s[17]) {
+    for (int i = 0; i < 3; ++i) { y.p[i] = s[i]; y.v[i] = s[7 + i]; y.w[i] = s[10 + i]; }
+    for (int i = 0; i < 4; ++i) y.q[i] = s[3 + i];
+}
+
+// Reverse of one sub-step starting at state s with action act; lam (17) is the
+// cotangent of the sub-step output and is overwritten with the cotangent of s;
+// la (4) accumulates the action cotangent.
+__device__ void substep_vjp(const DynConst& c, const float s[17], const float act[4], float lam[17], float la[4]) {
+    // ---- recompute the forward sub-step ----
+    float fraw[4], fdes[4], wd[4], w0[4], wh[4], wf[4];
+    if (c.ctrl == VF_SRT) {
+        for (int i = 0; i < 4; ++i) fraw[i] = act[i];
+    } else {
+        const float* om = s + 10;
+        float jo[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
+        float t0 = c.kJ[0] * (act[1] - om[0]) + (om[1] * jo[2] - om[2] * jo[1]);
+        float t1 = c.kJ[1] * (act[2] - om[1]) + (om[2] * jo[0] - om[0] * jo[2]);
+        float t2 = c.kJ[2] * (act[3] - om[2]) + (om[0] * jo[1] - om[1] * jo[0]);
+        float u0 = c.mass * act[0], u1 = t0 * c.inv_a, u2 = t1 * c.inv_a, u3 = t2 * c.inv_kappa;
+        fraw[0] = 0.25f * ((u0 + u3) - (u1 + u2));
+        fraw[1] = 0.25f * ((u0 + u3) + (u1 + u2));
+        fraw[2] = 0.25f * ((u0 - u3) + (u1 - u2));
+        fraw[3] = 0.25f * ((u0 - u3) - (u1 - u2));
+    }
+    for (int i = 0; i < 4; ++i) {
+        fdes[i] = fminf(fmaxf(fraw[i], 0.0f), c.f_max);
+        wd[i] = sqrtf(fdes[i]);
+        w0[i] = s[13 + i];
+        wh[i] = wd[i] + (w0[i] - wd[i]) * c.e_half;
+        wf[i] = wd[i] + (w0[i] - wd[i]) * c.e_full;
+    }
+    const float h = c.h;
+    Vec13 y, y1, y2, y3, k1, k2, k3, k4, yn;
+    load13(y, s);
+    derivative(c, y, w0, k1);
+    bool euler = c.integrator == VF_EULER;
+    if (euler) {
+        axpy13(yn, y, h, k1);
+    } else {
+        axpy13(y1, y, 0.5f * h, k1);
+        derivative(c, y1, wh, k2);
+        axpy13(y2, y, 0.5f * h, k2);
+        derivative(c, y2, wh, k3);
+        axpy13(y3, y, h, k3);
+        derivative(c, y3, wf, k4);
+        const float h6 = h * (1.0f / 6.0f);
+        for (int i = 0; i < 3; ++i) {
+            yn.p[i] = y.p[i] + h6 * (k1.p[i] + 2.0f * (k2.p[i] + k3.p[i]) + k4.p[i]);
+            yn.v[i] = y.v[i] + h6 * (k1.v[i] + 2.0f * (k2.v[i] + k3.v[i]) + k4.v[i]);
+            yn.w[i] = y.w[i] + h6 * (k1.w[i] + 2.0f * (k2.w[i] + k3.w[i]) + k4.w[i]);
+        }
+        for (int i = 0; i < 4; ++i) yn.q[i] = y.q[i] + h6 * (k1.q[i] + 2.0f * (k2.q[i] + k3.q[i]) + k4.q[i]);
+    }
+    // ---- reverse ----
+    float lwf[4], lwh[4] = {0.f, 0.f, 0.f, 0.f}, lw0[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i) lwf[i] = lam[13 + i];
+    Vec13 lyn;
+    for (int i = 0; i < 3; ++i) { lyn.p[i] = lam[i]; lyn.v[i] = lam[7 + i]; lyn.w[i] = lam[10 + i]; }
+    {
+        float lqn[4] = {lam[3], lam[4], lam[5], lam[6]};
+        normalize_vjp(yn.q, lqn, lyn.q);
+    }
+    Vec13 ly = lyn;
+    if (euler) {
+        Vec13 lk1, tmp;
+        zero13(tmp);
+        for (int i = 0; i < 3; ++i) { lk1.p[i] = h * lyn.p[i]; lk1.v[i] = h * lyn.v[i]; lk1.w[i] = h * lyn.w[i]; }
+        for (int i = 0; i < 4; ++i) lk1.q[i] = h * lyn.q[i];
+        derivative_vjp(c, y, w0, lk1, ly, lw0);
+    } else {
+        const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
+        Vec13 lk1, lk2, lk3, lk4, l3, l2, l1;
+        for (int i = 0; i < 3; ++i) {
+            lk1.p[i] = h6 * lyn.p[i]; lk2.p[i] = h3 * lyn.p[i]; lk3.p[i] = h3 * lyn.p[i]; lk4.p[i] = h6 * lyn.p[i];
+            lk1.v[i] = h6 * lyn.v[i]; lk2.v[i] = h3 * lyn.v[i]; lk3.v[i] = h3 * lyn.v[i]; lk4.v[i] = h6 * lyn.v[i];
+            lk1.w[i] = h6 * lyn.w[i]; lk2.w[i] = h3 * lyn.w[i]; lk3.w[i] = h3 * lyn.w[i]; lk4.w[i] = h6 * lyn.w[i];
+        }
+        for (int i = 0; i < 4; ++i) {
+            lk1.q[i] = h6 * lyn.q[i]; lk2.q[i] = h3 * lyn.q[i]; lk3.q[i] = h3 * lyn.q[i]; lk4.q[i] = h6 * lyn.q[i];
+        }
+        // k4 = F(y3, wf), y3 = y + h k3
+        zero13(l3);
+        derivative_vjp(c, y3, wf, lk4, l3, lwf);
+        axpy13(ly, ly, 1.0f, l3);
+        axpy13(lk3, lk3, h, l3);
+        // k3 = F(y2, wh), y2 = y + h/2 k2
+        zero13(l2);
+        derivative_vjp(c, y2, wh, lk3, l2, lwh);
+        axpy13(ly, ly, 1.0f, l2);
+        axpy13(lk2, lk2, 0.5f * h, l2);
+        // k2 = F(y1, wh), y1 = y + h/2 k1
+        zero13(l1);
+        derivative_vjp(c, y1, wh, lk2, l1, lwh);
+        axpy13(ly, ly, 1.0f, l1);
+        axpy13(lk1, lk1, 0.5f * h, l1);
+        // k1 = F(y, w0)
+        derivative_vjp(c, y, w0, lk1, ly, lw0);
+    }
+    // rotor lag: wh = wd + (w0 - wd) e_half, wf = wd + (w0 - wd) e_full
+    float lwd[4], lf[4];
+    for (int i = 0; i < 4; ++i) {
+        lw0[i] += c.e_half * lwh[i] + c.e_full * lwf[i];
+        lwd[i] = (1.0f - c.e_half) * lwh[i] + (1.0f - c.e_full) * lwf[i];
+        // wd = sqrt(fdes), fdes = clamp(fraw)
+        bool inside = fraw[i] > 0.0f && fraw[i] < c.f_max;
+        lf[i] = (inside && wd[i] > 0.0f) ? lwd[i] * 0.5f / wd[i] : 0.0f;
+    }
+    float lom_ctrl[3] = {0.f, 0.f, 0.f};
+    if (c.ctrl == VF_SRT) {
+        for (int i = 0; i < 4; ++i) la[i] += lf[i];
+    } else {
+        float lu0 = 0.25f * ((lf[0] + lf[1]) + (lf[2] + lf[3]));
+        float lu1 = 0.25f * ((lf[1] + lf[2]) - (lf[0] + lf[3]));
+        float lu2 = 0.25f * ((lf[1] + lf[3]) - (lf[0] + lf[2]));
+        float lu3 = 0.25f * ((lf[0] + lf[1]) - (lf[2] + lf[3]));
+        float lt[3] = {lu1 * c.inv_a, lu2 * c.inv_a, lu3 * c.inv_kappa};
+        la[0] += c.mass * lu0;
+        for (int k = 0; k < 3; ++k) {
+            la[1 + k] += c.kJ[k] * lt[k];
+            lom_ctrl[k] -= c.kJ[k] * lt[k];
+        }
+        float g[3];
+        gyro_vjp(c, s + 10, lt, g);
+        for (int k = 0; k < 3; ++k) lom_ctrl[k] += g[k];
+    }
+    for (int i = 0; i < 3; ++i) {
+        lam[i] = ly.p[i];
+        lam[7 + i] = ly.v[i];
+        lam[10 + i] = ly.w[i] + lom_ctrl[i];
+    }
+    for (int i = 0; i < 4; ++i) {
+        lam[3 + i] = ly.q[i];
+        lam[13 + i] = lw0[i];
+    }
+}
+
+// One forward sub-step in place (same arithmetic as dyn_step's loop body).
+__device__ __forceinline__ void substep_fwd(const DynConst& c, float s[17], const float a[4]) {
+    DynConst one = c;
+    one.n_sub = 1;
+    dyn_step(one, s, a, s);
+}
+
+__global__ void __launch_bounds__(128) k_step_backward(StepBackArgs a) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    float s0[17], act[4], lam[17], la[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 17; ++k) {
+        s0[k] = a.state_in[(int64_t)i * 17 + k];
+        lam[k] = a.grad_out[(int64_t)i * 17 + k];
+    }
+    for (int k = 0; k < 4; ++k) act[k] = a.action[(int64_t)i * 4 + k];
+    for (int sub = a.dyn.n_sub - 1; sub >= 0; --sub) {
+        float s[17];
+        for (int k = 0; k < 17; ++k) s[k] = s0[k];
+        for (int j = 0; j < sub; ++j) substep_fwd(a.dyn, s, act);
+        substep_vjp(a.dyn, s, act, lam, la);
+    }
+    for (int k = 0; k < 17; ++k) a.grad_in[(int64_t)i * 17 + k] = lam[k];
+    for (int k = 0; k < 4; ++k) a.grad_action[(int64_t)i * 4 + k] = la[k];
+}
+
+constexpr int kBackThreads = 256;
+
+__global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs a) {
+    __shared__ float red[12][kBackThreads];
+    const int agent = blockIdx.x;
+    vf_view vw = a.views[agent];
+    bool ok = vw.scene_id >= 0 && vw.scene_id < a.n_scenes && vw.H >= 1 && vw.W >= 1 && vw.H <= a.max_h &&
+              vw.W <= a.max_w && vw.out_offset >= 0 && vw.out_offset + (int64_t)vw.H * vw.W <= a.out_pixels &&
+              vw.hfov > 0.f && vw.hfov < 3.1415926f;
+    if (ok) ok = a.scenes[vw.scene_id].valid != 0;
+    if (!ok) {
+        if (threadIdx.x == 0) atomicOr(a.err, kErrView);
+        return;
+    }
+    const SceneDesc sc = a.scenes[vw.scene_id];
+    const float* st = a.state + (int64_t)agent * 17;
+    float q[4] = {st[3], st[4], st[5], st[6]};
+    float rot[9];
+    quat_rot(q, rot);
+    const float o[3] = {st[0], st[1], st[2]};
+    const float tan_h = tanf(0.5f * vw.hfov);
+    float acc[12];
+    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
+    uint32_t bad = 0;
+    const int npix = vw.H * vw.W;
+    for (int pix = threadIdx.x; pix < npix; pix += kBackThreads) {
+        int64_t at = vw.out_offset + pix;
+        int32_t id = a.tri_id[at];
+        float g = a.grad_depth[at];
+        if (id < 0 || g == 0.0f) continue;
+        if (id >= sc.n_tris) {
+            bad = kErrTriId;
+            continue;
+        }
+        const Tri tr = sc.tris[sc.sorted_of[id]];
+        int r = pix / vw.W, cc = pix - r * vw.W;
+        float u = (2.0f * ((float)cc + 0.5f) / (float)vw.W - 1.0f) * tan_h;
+        float v = (1.0f - 2.0f * ((float)r + 0.5f) / (float)vw.H) * tan_h * ((float)vw.H / (float)vw.W);
+        float db[3] = {1.0f, -u, v};
+        float d[3] = {rot[0] + rot[1] * db[1] + rot[2] * db[2], rot[3] + rot[4] * db[1] + rot[5] * db[2],
+                      rot[6] + rot[7] * db[1] + rot[8] * db[2]};
+        float n[3] = {tr.e1y * tr.e2z - tr.e1z * tr.e2y, tr.e1z * tr.e2x - tr.e1x * tr.e2z,
+                      tr.e1x * tr.e2y - tr.e1y * tr.e2x};
+        float nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+        if (nd == 0.0f) continue;
+        float t = (n[0] * (tr.v0x - o[0]) + n[1] * (tr.v0y - o[1]) + n[2] * (tr.v0z - o[2])) / nd;
+        float s_o = -g / nd, s_d = -g * t / nd;
+        for (int k = 0; k < 3; ++k) acc[k] += s_o * n[k];
+        for (int i2 = 0; i2 < 3; ++i2)
+            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * n[i2] * db[j];
+    }
+    if (bad) atomicOr(a.err, bad);
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kBackThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 12; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float* gs = a.grad_state + (int64_t)agent * 17;
+        for (int k = 0; k < 3; ++k) gs[k] += red[k][0];
+        float G[9];
+        for (int k = 0; k < 9; ++k) G[k] = red[3 + k][0];
+        float inv = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        float qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
+        float lqn[4], lq[4];
+        rot_vjp(qn, G, lqn);
+        normalize_vjp(q, lqn, lq);
+        for (int k = 0; k < 4; ++k) gs[3 + k] += lq[k];
+    }
+}
+
+hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step_backward, dim3((a.n + 127) / 128), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render_backward, dim3(a.n), dim3(kBackThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace vf

@@ -1,0 +1,198 @@
+// Internal definitions shared by the HIP sources of the library (device structs,
+// launch constants, the context).  Not part of the public ABI (include/visfly.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/visfly.h"
+
+namespace vf {
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
+constexpr int kWavesPerBlock = 4;     // render workgroup = 4 wavefronts = 4 tiles
+constexpr int kLeafMax = 4;           // triangles per BVH leaf
+constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
+constexpr int kMaxBvhDepth = 40;      // builds deeper than this are rejected (3 pushes per level)
+constexpr int kMaxScenes = 1024;
+constexpr int kMaxImage = 1024;
+
+// sticky device error bits
+enum : uint32_t {
+    kErrScene = 1u << 0,      // scene id out of range or freed
+    kErrSlot = 1u << 1,       // env_idx out of [0, n_slots)
+    kErrPixels = 1u << 2,     // out_offset + H*W beyond out_pixels (or negative)
+    kErrView = 1u << 3,       // H, W outside [1, max], bad hfov
+    kErrStack = 1u << 4,      // traversal stack overflow
+    kErrTriIndex = 1u << 5,   // scene build: vertex index out of range
+    kErrTriId = 1u << 6,      // render_backward: tri id out of range
+};
+
+// ---------------------------------------------------------------------------
+// device scene layout
+// ---------------------------------------------------------------------------
+struct alignas(16) Node4 {
+    float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+    int32_t child[4];
+    uint8_t count[4];
+    uint32_t order_lo, order_hi;
+    uint32_t pad;
+};
+static_assert(sizeof(Node4) == 128, "node is two 64-byte lines");
+static_assert(sizeof(Node4) == sizeof(vf_bvh4_node), "node matches the exported layout");
+
+struct alignas(16) Tri {
+    float v0x, v0y, v0z; int32_t id;
+    float e1x, e1y, e1z, pad1;
+    float e2x, e2y, e2z, pad2;
+};
+static_assert(sizeof(Tri) == 48, "triangle record is 48 bytes");
+static_assert(sizeof(Tri) == sizeof(vf_tri), "triangle matches the exported layout");
+
+// One entry of the device scene table (64 bytes).
+struct alignas(16) SceneDesc {
+    const Node4* nodes;
+    const Tri* tris;          // sorted leaf order
+    const uint8_t* rgb;       // [T][3] caller order, or null
+    const int32_t* sorted_of; // caller triangle index -> sorted position
+    int32_t n_tris;
+    int32_t root_leaf;        // 1: the whole scene is one leaf (T <= kLeafMax), no nodes
+    int32_t valid;
+    int32_t pad[5];
+};
+static_assert(sizeof(SceneDesc) == 64, "scene table entry is 64 bytes");
+
+// ---------------------------------------------------------------------------
+// dynamics constants, derived once per call on the host
+// ---------------------------------------------------------------------------
+struct DynConst {
+    float h;              // sub-step length dt / n_sub
+    int32_t n_sub, integrator, ctrl;
+    float mass, inv_mass, g;
+    float J[3], inv_J[3];
+    float kJ[3];          // J * k_rate
+    float arm_a, inv_a;   // arm / sqrt(2) and its reciprocal
+    float kappa, inv_kappa, f_max;
+    float k_lin[3], c_quad[3];
+    float e_half, e_full; // exp(-h / (2 tau)), exp(-h / tau)
+};
+
+DynConst make_dyn_const(const vf_dyn_params& p);
+bool check_dyn_params(const vf_dyn_params& p, std::string* why);
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct SceneHost {
+    bool used = false;
+    void* block = nullptr;      // one device allocation holding everything below
+    int64_t bytes = 0;
+    vf_scene_info info{};
+    SceneDesc desc{};
+};
+
+struct Counters {               // per state buffer arrival counters of the fused kernel
+    const float* state = nullptr;
+    int32_t* counters = nullptr;
+    int64_t capacity = 0;
+};
+
+}  // namespace vf
+
+struct vf_ctx {
+    int device = 0;
+    int n_cu = 0;
+    int64_t budget = 0;
+    int64_t used = 0;
+    std::mutex mu;
+    std::vector<vf::SceneHost> scenes;
+    vf::SceneDesc* d_scenes = nullptr;     // device scene table [kMaxScenes]
+    uint32_t* d_err = nullptr;             // sticky error word
+    unsigned long long* d_stats = nullptr; // 8 counters
+    bool stats = false;
+    std::vector<vf::Counters> counters;
+};
+
+namespace vf {
+// ---------------------------------------------------------------------------
+// kernel launch arguments (passed by value)
+// ---------------------------------------------------------------------------
+struct RenderArgs {
+    const SceneDesc* scenes;
+    int32_t n_scenes;
+    int32_t n;
+    const int32_t* env_idx;
+    float* state;
+    int64_t n_slots;
+    const float* action;
+    const vf_view* views;
+    int32_t max_h, max_w;
+    int32_t groups_per_agent;
+    int32_t total_groups;
+    float* depth;
+    int32_t* tri_id;
+    uint8_t* rgb;
+    int64_t out_pixels;
+    uint32_t* err;
+    unsigned long long* stats;
+    int32_t* counters;
+    DynConst dyn;
+};
+struct StepArgs {
+    int32_t n;
+    const int32_t* env_idx;
+    float* state;
+    int64_t n_slots;
+    const float* action;
+    uint32_t* err;
+    DynConst dyn;
+};
+struct StepBackArgs {
+    int32_t n;
+    const float* state_in;
+    const float* action;
+    const float* grad_out;
+    float* grad_in;
+    float* grad_action;
+    DynConst dyn;
+};
+struct RenderBackArgs {
+    const SceneDesc* scenes;
+    int32_t n_scenes;
+    int32_t n;
+    const float* state;
+    const vf_view* views;
+    int32_t max_h, max_w;
+    const int32_t* tri_id;
+    const float* grad_depth;
+    int64_t out_pixels;
+    float* grad_state;
+    uint32_t* err;
+};
+hipError_t launch_step(const StepArgs& a, hipStream_t st);
+hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st);
+hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);
+hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st);
+vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t* tris, int32_t nt,
+                      const uint8_t* rgb, hipStream_t st, SceneHost* out);
+
+void set_error(const std::string& msg);
+vf_status fail(vf_status st, const std::string& msg);
+vf_status hip_fail(hipError_t e, const char* what);
+vf_status ctx_alloc(vf_ctx* ctx, void** p, int64_t bytes);
+void ctx_free(vf_ctx* ctx, void* p, int64_t bytes);
+}  // namespace vf
+
+#define VF_HIP(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return vf::hip_fail(e_, #call); \
+    } while (0)

@@ -1,0 +1,167 @@
+"""Torch-facing wrapper over the C ABI.  Torch supplies device memory and streams only;
+every step of the path runs in the library's HIP kernels."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import check, lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_views(views, n):
+    if views is not None and views.numel() * views.element_size() < 40 * n:
+        raise ValueError(f"views holds fewer than n = {n} entries")
+
+
+def _check_rows(t, n, cols, name):
+    if t is not None and (t.numel() < n * cols):
+        raise ValueError(f"{name} holds fewer than {n} x {cols} values")
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_views(n, scene_ids, hw, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None, device="cuda"):
+    """Per-agent view array [n] on the device plus (out_pixels, offsets, max_h, max_w).
+
+    scene_ids: int or [n]; hw: (H, W) or [n, 2]; outputs are packed agent after agent.
+    """
+    scene_ids = np.broadcast_to(np.asarray(scene_ids, dtype=np.int64).reshape(-1), (n,))
+    hw = np.broadcast_to(np.asarray(hw, dtype=np.int64).reshape(-1, 2), (n, 2))
+    v = np.zeros(n, dtype=capi.VIEW_DTYPE)
+    v["scene_id"] = scene_ids
+    v["H"] = hw[:, 0]
+    v["W"] = hw[:, 1]
+    v["hfov"] = hfov
+    v["near_clip"] = near
+    v["far_clip"] = far
+    v["miss_depth"] = far if miss_depth is None else miss_depth
+    px = hw[:, 0] * hw[:, 1]
+    offsets = np.concatenate([[0], np.cumsum(px)[:-1]]).astype(np.int64)
+    v["out_offset"] = offsets
+    dev = torch.from_numpy(v.view(np.uint8).copy()).to(device)
+    return dev, int(px.sum()), offsets, int(hw[:, 0].max()), int(hw[:, 1].max())
+
+
+class Context:
+    """One library context on one GPU (scenes, scratch, counters)."""
+
+    def __init__(self, device=0, budget_bytes=0):
+        torch.cuda.init()
+        self.device = device
+        h = ctypes.c_void_p()
+        check(lib.vf_create(device, budget_bytes, ctypes.byref(h)), "vf_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(lib.vf_destroy(self.h), "vf_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- scenes
+    def build_scene(self, verts, tris, rgb=None, stream=None):
+        v = torch.as_tensor(np.asarray(verts, dtype=np.float32)).cuda(self.device).contiguous()
+        t = torch.as_tensor(np.asarray(tris, dtype=np.int32)).cuda(self.device).contiguous()
+        c = None if rgb is None else torch.as_tensor(np.asarray(rgb, dtype=np.uint8)).cuda(self.device).contiguous()
+        sid = ctypes.c_int32(-1)
+        check(lib.vf_scene_build(self.h, _ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(c), _stream(stream),
+                                 ctypes.byref(sid)), "vf_scene_build")
+        return sid.value
+
+    def free_scene(self, sid):
+        check(lib.vf_scene_free(self.h, sid), "vf_scene_free")
+
+    def scene_info(self, sid):
+        info = capi.SceneInfo()
+        check(lib.vf_scene_info_get(self.h, sid, ctypes.byref(info)), "vf_scene_info_get")
+        return {"n_tris": info.n_tris, "n_nodes": info.n_nodes, "bytes": info.bytes, "depth": info.depth,
+                "leaf_max": info.leaf_max, "bounds_lo": list(info.bounds_lo), "bounds_hi": list(info.bounds_hi),
+                "build_ms": info.build_ms}
+
+    def export_scene(self, sid):
+        info = self.scene_info(sid)
+        nodes = np.zeros(info["n_nodes"], dtype=capi.NODE_DTYPE)
+        tris = np.zeros(info["n_tris"], dtype=capi.TRI_DTYPE)
+        check(lib.vf_scene_export(self.h, sid, nodes.ctypes.data_as(ctypes.c_void_p), nodes.nbytes,
+                                  tris.ctypes.data_as(ctypes.c_void_p), tris.nbytes), "vf_scene_export")
+        return nodes, tris
+
+    # ---------------------------------------------------------------- step / render
+    def step(self, params, state, action, views=None, env_idx=None, max_hw=(0, 0), depth=None, tri_id=None,
+             rgb=None, out_pixels=0, stream=None):
+        p = params if isinstance(params, capi.DynParams) else capi.params_struct(params)
+        n = action.shape[0]
+        _check_views(views, n)
+        if env_idx is not None and env_idx.numel() < n:
+            raise ValueError("env_idx holds fewer than n entries")
+        if env_idx is None:
+            _check_rows(state, n, 17, "state")
+        check(lib.vf_step(self.h, ctypes.byref(p), n, _ptr(env_idx), _ptr(state), state.shape[0], _ptr(action),
+                          _ptr(views), int(max_hw[0]), int(max_hw[1]), _ptr(depth), _ptr(tri_id), _ptr(rgb),
+                          int(out_pixels), _stream(stream)), "vf_step")
+
+    def render(self, state, views, n=None, env_idx=None, max_hw=(64, 64), depth=None, tri_id=None, rgb=None,
+               out_pixels=0, stream=None):
+        n = state.shape[0] if n is None else n
+        _check_views(views, n)
+        if env_idx is not None and env_idx.numel() < n:
+            raise ValueError("env_idx holds fewer than n entries")
+        if env_idx is None:
+            _check_rows(state, n, 17, "state")
+        check(lib.vf_render(self.h, n, _ptr(env_idx), _ptr(state), state.shape[0], _ptr(views), int(max_hw[0]),
+                            int(max_hw[1]), _ptr(depth), _ptr(tri_id), _ptr(rgb), int(out_pixels),
+                            _stream(stream)), "vf_render")
+
+    def step_backward(self, params, state_in, action, grad_out, grad_in, grad_action, stream=None):
+        n = state_in.shape[0]
+        for t, c, nm in ((action, 4, "action"), (grad_out, 17, "grad_out"), (grad_in, 17, "grad_in"),
+                         (grad_action, 4, "grad_action")):
+            _check_rows(t, n, c, nm)
+        p = params if isinstance(params, capi.DynParams) else capi.params_struct(params)
+        check(lib.vf_step_backward(self.h, ctypes.byref(p), state_in.shape[0], _ptr(state_in), _ptr(action),
+                                   _ptr(grad_out), _ptr(grad_in), _ptr(grad_action), _stream(stream)),
+              "vf_step_backward")
+
+    def render_backward(self, state, views, max_hw, tri_id, grad_depth, out_pixels, grad_state, stream=None):
+        _check_views(views, state.shape[0])
+        _check_rows(grad_state, state.shape[0], 17, "grad_state")
+        check(lib.vf_render_backward(self.h, state.shape[0], _ptr(state), _ptr(views), int(max_hw[0]),
+                                     int(max_hw[1]), _ptr(tri_id), _ptr(grad_depth), int(out_pixels),
+                                     _ptr(grad_state), _stream(stream)), "vf_render_backward")
+
+    # ---------------------------------------------------------------- diagnostics
+    def sync_check(self, stream=None):
+        check(lib.vf_sync_check(self.h, _stream(stream)), "vf_sync_check")
+
+    def set_stats(self, on):
+        check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")
+
+    def read_stats(self, reset=True):
+        out = (ctypes.c_uint64 * 8)()
+        check(lib.vf_stats_read(self.h, out, 1 if reset else 0), "vf_stats_read")
+        keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_lane_active", "hits")
+        return dict(zip(keys, list(out)))
+
+    def mem_usage(self):
+        u, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib.vf_mem_usage(self.h, ctypes.byref(u), ctypes.byref(b)), "vf_mem_usage")
+        return u.value, b.value

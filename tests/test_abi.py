@@ -1,0 +1,47 @@
+"""The C-ABI library loads on the host and exports every entry point include/visfly.h declares (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "visfly.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:vf_status|const char\*)\s+(vf_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("vf_scene_build", "vf_step", "vf_render", "vf_step_backward", "vf_render_backward",
+                     "vf_create", "vf_destroy", "vf_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2407_14783_amd import capi
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    names = _declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+    assert sorted(capi.EXPORTED) == names
+
+
+def test_struct_layouts_match_header():
+    from paper_2407_14783_amd import capi
+    assert ctypes.sizeof(capi.DynParams) == 88
+    assert capi.VIEW_DTYPE.itemsize == 40 and capi.VIEW_DTYPE.fields["out_offset"][1] == 32
+    assert capi.NODE_DTYPE.itemsize == 128 and capi.TRI_DTYPE.itemsize == 48
+    assert capi.NODE_DTYPE.fields["child"][1] == 96 and capi.NODE_DTYPE.fields["count"][1] == 112
+
+
+def test_params_struct_roundtrip():
+    from paper_2407_14783_amd import capi
+    from workloads import default_params
+    p = default_params()
+    s = capi.params_struct(p)
+    raw = np.frombuffer(bytes(s), dtype=np.float32)
+    assert np.isclose(raw[0], p["dt"]) and np.isclose(s.f_max, p["f_max"]) and list(s.k_rate) == [20.0, 20.0, 10.0]
