@@ -1,0 +1,200 @@
+"""Benchmark of the batched quadrotor step + ray-cast render on one MI355X.
+
+A step is one fused vf_step launch over the whole batch: CTBR controller, rotor
+lag, RK4 (Sec. III-A) and the 64x64 depth / triangle id / colour render of every
+agent at its new pose (Sec. III-B), on synthetic inputs resident in HBM.
+
+Default workload ("forest-256"): 256 agents in a seeded procedural forest of
+2,000 open 32-segment cylinders on a 40 x 40 m ground quad (128,002 triangles),
+64x64 depth + tri id + RGB, dt = 0.02 s, 200 seeded CTBR action steps (cycled).
+
+Printed: one JSON line with frames/s, ms/step, the roofline of the fused kernel
+(ALU-bound: VALU lane-operations of the ray-box and ray-triangle tests it
+performs, counted by a replay with the counting kernel variant, over its
+HIP-event time), HBM traffic if supplied from rocprofv3 counters, the serving
+latency of the continuous-batching loop, and the FP64 oracle timed on the host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 latency"
+# VALU lane-operations per test as issued by the traversal kernel:
+OPS_PER_BOX = 26       # 6 sub + 6 mul slab distances, 12 min/max, 1 mul (Ize growth), 1 compare
+OPS_PER_TRI = 55       # Moller-Trumbore: 2 cross products, 3 dots, 3 subs, rcp, 3 muls, compares, selects
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--agents", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-stats", action="store_true", help="skip the counting replay (profiling runs)")
+    ap.add_argument("--traffic-kib", type=str, default=None,
+                    help="FETCH,WRITE KiB per dispatch of the fused kernel from rocprofv3 (scaled)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for counter scaling)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 5}))
+
+
+def cpu_baseline(sc, s0, acts, params, budget_s):
+    """The oracle (FP64 dynamics + brute-force render, as it stands) on a bounded sample."""
+    from oracle import dynamics as odyn
+    from oracle import render as oren
+    n_agents = min(4, s0.shape[0])
+    s = s0[:n_agents].astype(np.float64)
+    frames = 0
+    threads = 1
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        s = odyn.step(s, acts[k % acts.shape[0]][:n_agents], params)
+        for i in range(n_agents):
+            r = oren.render_view(s[i], sc, 64, 64, math.pi / 2, with_mask=False)
+            threads = r["threads"]
+            frames += 1
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_agents} agents x {k} steps of the forest-256 workload (FP64 RK4 + brute-force "
+                      f"all-triangle ray casting, {frames} frames, {dt:.1f} s)"}
+
+
+def serving_summary(ctx, sim, params):
+    from paper_2407_14783_amd import serving
+    return serving.bench_summary(ctx, params)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(agents shard by scene with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import torch
+    from paper_2407_14783_amd import sim
+    from workloads import agents, default_params, scenes
+
+    params = default_params()
+    n = args.agents
+    sc = scenes.forest(seed=3)
+    s0 = agents.forest_starts(4, n, sc, params)
+    acts_np = agents.random_actions(5, 200, n, params)
+    ctx = sim.Context(0)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    info = ctx.scene_info(sid)
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+    state = torch.as_tensor(s0).cuda()
+    acts = torch.as_tensor(acts_np).cuda()
+    depth = torch.empty(npx, device="cuda")
+    tri_id = torch.empty(npx, dtype=torch.int32, device="cuda")
+    rgb = torch.empty(3 * npx, dtype=torch.uint8, device="cuda")
+    pstruct = sim.capi.params_struct(params)
+    stream = torch.cuda.current_stream()
+
+    def run(k0, k1):
+        for k in range(k0, k1):
+            ctx.step(pstruct, state, acts[k % 200], views=views, max_hw=(mh, mw), depth=depth, tri_id=tri_id,
+                     rgb=rgb, out_pixels=npx, stream=stream)
+
+    run(0, args.warmup)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(args.warmup, args.warmup + args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync_check()
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+    frames_per_s = n * args.steps / (gpu_ms / 1e3)
+    hit_frac = float((tri_id >= 0).float().mean().item())
+
+    out = {"metric": METRIC, "value": frames_per_s, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "forest-256", "agents": n, "scene_triangles": int(info["n_tris"]),
+                      "image": "64x64", "outputs": "depth f32 + tri id i32 + RGB u8", "controller": "CTBR",
+                      "integrator": "RK4", "dt": params["dt"], "bvh_nodes": int(info["n_nodes"]),
+                      "bvh_depth": int(info["depth"]), "scene_build_ms": round(float(info["build_ms"]), 3)},
+           "wall_s": wall, "hit_fraction": hit_frac}
+
+    if not args.no_stats:
+        # replay the same steps with the counting kernel variant (not timed)
+        state.copy_(torch.as_tensor(s0).cuda())
+        run(0, args.warmup)
+        torch.cuda.synchronize()
+        ctx.read_stats(reset=True)
+        ctx.set_stats(True)
+        run(args.warmup, args.warmup + args.steps)
+        ctx.set_stats(False)
+        st = ctx.read_stats(reset=True)
+        box = st["box_lane"] / args.steps
+        tri = st["tri_lane"] / args.steps
+        ops = box * OPS_PER_BOX + tri * OPS_PER_TRI
+        achieved = ops / (ms_per_step / 1e3) / 1e12
+        rays = st["rays"] / args.steps
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                           "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                           "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
+                                          "wave_node_visits": st["node_wave"] / args.steps,
+                                          "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
+                                          "valu_ops": ops}}
+        out["ray_tri_tests_per_s"] = tri / (ms_per_step / 1e3)
+        out["rays_per_s"] = rays / (ms_per_step / 1e3)
+    if args.traffic_kib:
+        fetch_kib, write_kib = (float(x) for x in args.traffic_kib.split(","))
+        traffic = (fetch_kib + write_kib) * 1024.0
+        if "roofline" in out:
+            out["roofline"]["traffic"] = traffic
+        out["hbm"] = {"bytes_per_launch": traffic, "achieved_GBps": traffic / (ms_per_step / 1e3) / 1e9,
+                      "peak_GBps": HBM_PEAK_GBPS, "frac": traffic / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBPS}
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_summary(ctx, sim, params)
+        except ImportError:
+            out["serving"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, s0, acts_np, params, args.cpu_seconds)
+    ctx.free_scene(sid)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -170,7 +170,8 @@ vf_status vf_scene_export(vf_ctx* ctx, int32_t scene_id, void* nodes_host, int64
  * max_h/max_w bound every views[i].H/W (agents beyond them are rejected on the
  * device).  depth [dev] float32, tri_id [dev] int32, rgb [dev] uint8: each may
  * be NULL to skip that output; out_pixels = pixel capacity of depth/tri_id.
- * With views the step and the render run in one fused kernel launch. */
+ * With views the render follows the step on the same stream (see
+ * vf_set_launch_mode for the single-launch fused form). */
 vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int32_t* env_idx,
                   float* state, int64_t n_slots, const float* action,
                   const vf_view* views, int32_t max_h, int32_t max_w,
@@ -202,6 +203,16 @@ vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, 
 vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const vf_view* views,
                              int32_t max_h, int32_t max_w, const int32_t* tri_id, const float* grad_depth,
                              int64_t out_pixels, float* grad_state, void* stream);
+
+/* How vf_step with views launches its work.  VF_LAUNCH_SPLIT (the default):
+ * a dynamics kernel (one thread per agent) then the render kernel, two
+ * launches on the stream.  VF_LAUNCH_FUSED: one kernel in which every render
+ * workgroup advances its agent's dynamics in one lane and the last workgroup
+ * of the agent to finish writes the new state.  Both give bitwise identical
+ * states and images; the split form keeps the render kernel at its lower
+ * register count and is faster for batches that fill the GPU. */
+enum { VF_LAUNCH_SPLIT = 0, VF_LAUNCH_FUSED = 1 };
+vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode);
 
 /* Enable (1) / disable (0) traversal statistics: while enabled, vf_step and
  * vf_render use a counting variant of the render kernel that accumulates node

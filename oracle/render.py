@@ -133,6 +133,33 @@ def camera_rays(state_row, h, w, hfov):
     return s[0:3].copy(), d
 
 
+def frustum_keep(state_row, verts, tris, h, w, hfov, near, far, margin=1e-3):
+    """Triangles that can meet a ray of this view: False only when all three vertices lie outside
+    one bounding plane of the view's truncated pyramid, widened by `margin`.
+
+    In camera coordinates X_B = R^T (X - o) a ray t (1, -u, v) reaches exactly the points with
+    x_B = t in [near, far], -y_B / x_B = u and z_B / x_B = v; u and v range over the pixel centres.
+    A triangle is convex, so if every vertex violates the same half-space no point of it is
+    reachable.  The margin (relative, in u, v and t) keeps triangles that pass just outside the
+    view, so the near-miss data of boundary rays is unchanged.
+    """
+    s = np.asarray(state_row, dtype=np.float64)
+    rot = quat_to_rot(s[3:7])
+    v = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tris, dtype=np.int64)
+    xb = (v - s[0:3]) @ rot            # rows: (x_B, y_B, z_B) = R^T (X - o)
+    p = xb[t]                          # [T, 3 vertices, 3]
+    x, y, z = p[..., 0], p[..., 1], p[..., 2]
+    th = np.tan(0.5 * hfov)
+    u_max = (1.0 - 1.0 / w) * th + margin
+    v_max = (1.0 - 1.0 / h) * th * h / w + margin
+    lo, hi = near * (1.0 - margin), far * (1.0 + margin)
+    out = ((x < lo).all(1) | (x > hi).all(1)
+           | (-y > u_max * x).all(1) | (-y < -u_max * x).all(1)
+           | (z > v_max * x).all(1) | (z < -v_max * x).all(1))
+    return ~out
+
+
 def mask_from(out, eps_edge=1e-5, eps_tie=1e-5):
     """Pixels whose closest-hit id is not decided robustly (edges, near misses, ties, clip planes)."""
     t = out["t"]
@@ -145,17 +172,23 @@ def mask_from(out, eps_edge=1e-5, eps_tie=1e-5):
 
 
 def render_view(state_row, scene, h=64, w=64, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None,
-                eps_edge=1e-5, eps_tie=1e-5, with_mask=True, pixels=None):
+                eps_edge=1e-5, eps_tie=1e-5, with_mask=True, pixels=None, cull=True):
     """Depth [H,W] (or [P] for a pixel subset), triangle id, planar RGB and the comparison mask.
 
     pixels: optional int array of flat pixel indices (row * W + col) to render only those.
+    cull: pre-filter the triangles with frustum_keep() (exact: never changes a result).
     """
     miss_depth = far if miss_depth is None else miss_depth
     o, d = camera_rays(state_row, h, w, hfov)
     d = d.reshape(-1, 3)
     if pixels is not None:
         d = d[np.asarray(pixels)]
-    out = cast(o, d, scene["verts"], scene["tris"], near, far, with_mask=with_mask)
+    tris_all = np.asarray(scene["tris"])
+    keep = np.nonzero(frustum_keep(state_row, scene["verts"], tris_all, h, w, hfov, near, far))[0] if cull \
+        else np.arange(tris_all.shape[0])
+    out = cast(o, d, scene["verts"], tris_all[keep], near, far, with_mask=with_mask)
+    if keep.size:
+        out["id"] = np.where(out["id"] >= 0, keep[np.maximum(out["id"], 0)], -1)
     hit = out["id"] >= 0
     depth = np.where(hit, out["t"], miss_depth)
     rgb = np.zeros((3, d.shape[0]), dtype=np.uint8)

@@ -311,10 +311,16 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
         VF_HIP(launch_step(a, st));
         return VF_OK;
     }
-    int32_t* counters = counters_for(ctx, state, n_slots, &s);
-    if (!counters) return s;
     RenderArgs a = make_render_args(ctx, n, env_idx, state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
                                     out_pixels);
+    if (ctx->launch_mode == VF_LAUNCH_SPLIT) {
+        StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
+        VF_HIP(launch_step(sa, st));
+        VF_HIP(launch_render(a, false, ctx->stats, st));
+        return VF_OK;
+    }
+    int32_t* counters = counters_for(ctx, state, n_slots, &s);
+    if (!counters) return s;
     a.action = action;
     a.counters = counters;
     a.dyn = dc;
@@ -367,6 +373,13 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
     RenderBackArgs a{ctx->d_scenes, (int32_t)ctx->scenes.size(), (int32_t)n, state, views, max_h, max_w,
                      tri_id, grad_depth, out_pixels, grad_state, ctx->d_err};
     VF_HIP(launch_render_backward(a, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_launch_mode: NULL context");
+    if (mode != VF_LAUNCH_SPLIT && mode != VF_LAUNCH_FUSED) return fail(VF_EINVAL, "vf_set_launch_mode: bad mode");
+    ctx->launch_mode = mode;
     return VF_OK;
 }
 

@@ -118,6 +118,7 @@ struct vf_ctx {
     uint32_t* d_err = nullptr;             // sticky error word
     unsigned long long* d_stats = nullptr; // 8 counters
     bool stats = false;
+    int32_t launch_mode = VF_LAUNCH_SPLIT;
     std::vector<vf::Counters> counters;
 };
 

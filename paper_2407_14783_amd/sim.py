@@ -152,6 +152,10 @@ class Context:
     def sync_check(self, stream=None):
         check(lib.vf_sync_check(self.h, _stream(stream)), "vf_sync_check")
 
+    def set_launch_mode(self, fused):
+        check(lib.vf_set_launch_mode(self.h, capi.VF_LAUNCH_FUSED if fused else capi.VF_LAUNCH_SPLIT),
+              "vf_set_launch_mode")
+
     def set_stats(self, on):
         check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")
 

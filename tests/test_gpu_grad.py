@@ -1,0 +1,178 @@
+"""GPU adjoint kernels against FP64 central finite differences of the oracle.
+
+vf_step_backward: J_s^T lam and J_a^T lam of one control step against the
+oracle's central-difference Jacobians (h = 1e-6) at the same float32 inputs.
+vf_render_backward: sum_pixels g * d depth / d (p, q) against central
+differences of the oracle's brute-force depth, off the edge mask.
+Rollout: the checkpointed BPTT of the differentiable rollout against central
+differences of the oracle's rollout loss along seeded random directions
+(directions whose hit ids change between the +h and -h rollouts are dropped).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dynamics as odyn
+from oracle import gradients as ograd
+from oracle import render as oren
+from workloads import agents, default_params, scenes
+from tests.gpu_util import header
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vf():
+    from paper_2407_14783_amd import sim
+    ctx = sim.Context(0)
+    yield sim, ctx
+    ctx.close()
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-12))
+
+
+def _random_states(rng, n, p, rate=1.0):
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return agents.make_states(rng.uniform(-5, 5, (n, 3)), p, quat=q, vel=rng.normal(scale=1.5, size=(n, 3)),
+                              omega=rng.uniform(-rate, rate, (n, 3)),
+                              rotor=np.sqrt(p["mass"] * p["g"] / 4) * rng.uniform(0.8, 1.2, (n, 4)))
+
+
+@pytest.mark.parametrize("variant", ["ctbr", "ctbr_saturating", "srt", "euler_nsub2", "rk4_nsub3"])
+def test_step_backward_matches_fd_jacobian(vf, variant):
+    sim, ctx = vf
+    rng = np.random.default_rng({"ctbr": 1, "ctbr_saturating": 2, "srt": 3, "euler_nsub2": 4, "rk4_nsub3": 5}[variant])
+    if variant == "srt":
+        p = default_params(ctrl=odyn.SRT)
+    elif variant == "euler_nsub2":
+        p = default_params(integrator=odyn.EULER, n_sub=2)
+    elif variant == "rk4_nsub3":
+        p = default_params(n_sub=3)
+    else:
+        p = default_params()
+    n = 32
+    s = _random_states(rng, n, p)
+    if variant == "srt":
+        a = (p["mass"] * p["g"] / 4 * rng.uniform(0.7, 1.3, (n, 4))).astype(np.float32)
+    elif variant == "ctbr_saturating":
+        a = agents.random_actions(int(rng.integers(1 << 30)), 1, n, p)[0]
+    else:
+        a = np.concatenate([rng.uniform(0.8, 1.2, (n, 1)) * p["g"], rng.uniform(-0.5, 0.5, (n, 3))], 1).astype(
+            np.float32)
+    lam = rng.normal(size=(n, 17)).astype(np.float32)
+    g_in = torch.zeros((n, 17)).cuda()
+    g_a = torch.zeros((n, 4)).cuda()
+    header(f"step_backward: {variant}")
+    ctx.step_backward(p, _dev(s), _dev(a), _dev(lam), g_in, g_a)
+    torch.cuda.synchronize()
+    js, ja = ograd.step_jacobian(s.astype(np.float64), a.astype(np.float64), p)
+    ref_in = np.einsum("nij,ni->nj", js, lam.astype(np.float64))
+    ref_a = np.einsum("nij,ni->nj", ja, lam.astype(np.float64))
+    gi, ga = g_in.cpu().numpy(), g_a.cpu().numpy()
+    for i in range(n):
+        assert _rel(gi[i], ref_in[i]) <= 2e-4, f"{variant} agent {i}: state cotangent rel err {_rel(gi[i], ref_in[i]):.2e}"
+        if np.linalg.norm(ref_a[i]) > 1e-6:
+            assert _rel(ga[i], ref_a[i]) <= 2e-4, f"{variant} agent {i}: action cotangent rel err {_rel(ga[i], ref_a[i]):.2e}"
+        else:
+            assert np.linalg.norm(ga[i]) <= 1e-5
+
+
+def test_render_backward_matches_fd(vf):
+    sim, ctx = vf
+    p = default_params()
+    sc = scenes.box_room(seed=1)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    rng = np.random.default_rng(31)
+    n, h, w = 4, 16, 16
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    st = agents.make_states(rng.uniform([1, 1, 0.5], [9, 9, 3.5], size=(n, 3)), p, quat=q)
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (h, w))
+    ids = torch.zeros(npx, dtype=torch.int32).cuda()
+    depth = torch.zeros(npx).cuda()
+    ctx.render(_dev(st), views, max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+    g = rng.normal(size=npx).astype(np.float32)
+    view = {"H": h, "W": w, "hfov": math.pi / 2, "near": 0.01, "far": 100.0}
+    # zero the weight of pixels near edges (finite differences would straddle two triangles there)
+    for i in range(n):
+        ref = oren.render_view(st[i].astype(np.float64), sc, h, w, math.pi / 2, eps_edge=1e-3)
+        g[offs[i]:offs[i] + h * w][ref["mask"].reshape(-1)] = 0.0
+    base = rng.normal(size=(n, 17)).astype(np.float32)
+    grad_state = _dev(base)
+    header("render_backward: box room, 4 agents, 16x16")
+    ctx.render_backward(_dev(st), views, (mh, mw), ids, _dev(g), npx, grad_state)
+    ctx.sync_check()
+    got = grad_state.cpu().numpy() - base
+    for i in range(n):
+        fd = ograd.depth_pose_gradient(st[i].astype(np.float64), sc, view, np.arange(h * w))
+        expect = g[offs[i]:offs[i] + h * w].astype(np.float64) @ fd
+        assert _rel(got[i, 0:7], expect) <= 1e-3, f"agent {i}: rel err {_rel(got[i, 0:7], expect):.2e}"
+        assert np.allclose(got[i, 7:], 0.0, atol=1e-6)
+    ctx.free_scene(sid)
+
+
+def _crop_forest(sc, centers, radius):
+    """Ground plus the trees within `radius` (xy) of any of the given points."""
+    trees = sc["trees"]
+    d = np.min(np.hypot(trees[:, 0][:, None] - centers[None, :, 0], trees[:, 1][:, None] - centers[None, :, 1]), axis=1)
+    keep = np.nonzero(d < radius)[0]
+    tri_sel = [np.arange(2)] + [2 + 64 * k + np.arange(64) for k in keep]
+    tri_sel = np.concatenate(tri_sel)
+    return {"verts": sc["verts"], "tris": sc["tris"][tri_sel], "rgb": sc["rgb"][tri_sel]}
+
+
+@pytest.mark.parametrize("w_goal", [0.01, 0.0])
+def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
+    """Differentiable rollout: 4 agents in a forest, horizon 64, checkpoints every 8 steps, 64x64 depth."""
+    sim, ctx = vf
+    from paper_2407_14783_amd import autograd as vag
+    p = default_params()
+    full = scenes.forest(seed=3)
+    n, H = 4, 64
+    s0 = agents.forest_starts(8, n, full, p)
+    sc = _crop_forest(full, s0[:, 0:3], 6.0)
+    rng = np.random.default_rng(8)
+    acts = np.concatenate([rng.uniform(0.9, 1.15, (H, n, 1)) * p["g"], rng.uniform(-0.6, 0.6, (H, n, 3))],
+                          axis=2).astype(np.float32)
+    ang = rng.uniform(0, 2 * np.pi, n)
+    goals = (s0[:, 0:3] + np.stack([12 * np.cos(ang), 12 * np.sin(ang), np.zeros(n)], 1)).astype(np.float32)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+    s0_t = _dev(s0).requires_grad_(True)
+    a_t = _dev(acts).requires_grad_(True)
+    header(f"BPTT: 4 agents x 64 steps, k = 8, w_goal = {w_goal}")
+    states, depths = vag.rollout(ctx, p, s0_t, a_t, views, (mh, mw), npx, checkpoint_every=8)
+    d0 = 1.0
+    loss = torch.exp(-depths.double() / d0).view(H, n, 64 * 64).mean(dim=2).sum() + \
+        w_goal * ((states[:, :, 0:3].double() - _dev(goals).double()) ** 2).sum()
+    loss.backward()
+    g_s0 = s0_t.grad.cpu().numpy().astype(np.float64)
+    g_a = a_t.grad.cpu().numpy().astype(np.float64)
+    view = {"H": 64, "W": 64, "hfov": math.pi / 2, "near": 0.01, "far": 100.0}
+    l_ref = ograd.rollout_loss(s0, acts, p, sc, goals, view, d0=d0, w_goal=w_goal)
+    assert abs(loss.item() - l_ref) <= 1e-4 * abs(l_ref)
+    checked = 0
+    for j in range(3):
+        u_s = rng.normal(size=s0.shape)
+        u_a = rng.normal(size=acts.shape)
+        norm = math.sqrt((u_s ** 2).sum() + (u_a ** 2).sum())
+        u_s, u_a = u_s / norm, u_a / norm
+        fd, stable = ograd.rollout_directional(s0, acts, p, sc, goals, view, u_s, u_a, h=1e-6, d0=d0,
+                                               w_goal=w_goal)
+        ad = float((g_s0 * u_s).sum() + (g_a * u_a).sum())
+        print(f"[gpu-test] direction {j}: adjoint {ad:.6e} fd {fd:.6e} ids stable {stable}", flush=True)
+        if not stable:
+            continue
+        assert abs(ad - fd) <= 2e-3 * max(abs(fd), 1e-3), f"direction {j}: adjoint {ad} vs fd {fd}"
+        checked += 1
+    assert checked >= 2
+    ctx.free_scene(sid)

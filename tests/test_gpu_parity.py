@@ -300,7 +300,9 @@ def test_fused_step_render_equals_split_and_oracle(vf):
     header("fused vs split: 40 agents x 10 steps")
     for k in range(10):
         a = _dev(acts[k])
+        ctx.set_launch_mode(True)
         ctx.step(p, st_f, a, views=views, max_hw=(mh, mw), depth=d_f, tri_id=i_f, rgb=c_f, out_pixels=npx)
+        ctx.set_launch_mode(False)
         ctx.step(p, st_s, a)
         ctx.render(st_s, views, max_hw=(mh, mw), depth=d_s, tri_id=i_s, rgb=c_s, out_pixels=npx)
         assert torch.equal(st_f, st_s), f"state differs at step {k}"
@@ -327,6 +329,7 @@ def test_fused_in_place_with_env_slots(vf):
     a = agents.random_actions(3, 1, 4, p)[0]
     views, npx, offs, mh, mw = sim.make_views(4, sid, (128, 128))
     depth = torch.zeros(npx).cuda()
+    ctx.set_launch_mode(True)
     ctx.step(p, st, _dev(a), views=views, env_idx=torch.as_tensor(idx).cuda(), max_hw=(mh, mw), depth=depth,
              out_pixels=npx)
     ctx.sync_check()
@@ -341,6 +344,11 @@ def test_fused_in_place_with_env_slots(vf):
     ctx.sync_check()
     ref2 = odyn.step(ref, a, p)
     assert state_close(st.cpu().numpy()[idx], ref2) <= 1e-6
+    ctx.set_launch_mode(False)
+    ctx.step(p, st, _dev(a), views=views, env_idx=torch.as_tensor(idx).cuda(), max_hw=(mh, mw), depth=depth,
+             out_pixels=npx)
+    ctx.sync_check()
+    assert state_close(st.cpu().numpy()[idx], odyn.step(ref2, a, p)) <= 1e-6
     ctx.free_scene(sid)
 
 

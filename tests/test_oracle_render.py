@@ -282,3 +282,20 @@ def test_mask_fraction_small_on_box_room():
     r = ren.render_view(st, sc, 64, 64, math.radians(90))
     assert r["mask"].mean() < 0.02
     assert np.all(r["id"] >= 0)
+
+
+def test_frustum_prefilter_never_changes_a_result():
+    """The oracle's view-frustum pre-filter is exact: culled and unculled renders agree bit for bit."""
+    rng = np.random.default_rng(17)
+    sc = scenes.forest(seed=3, n_trees=120)
+    room = scenes.box_room(seed=1)
+    for scene, lo, hi in ((sc, [-15, -15, 0.5], [15, 15, 6]), (room, [0.5, 0.5, 0.3], [9.5, 9.5, 3.7])):
+        for _ in range(4):
+            q = rng.normal(size=4)
+            q /= np.linalg.norm(q)
+            st = _state(rng.uniform(lo, hi), q)
+            for hw, fov in (((24, 24), math.pi / 2), ((9, 20), 1.1)):
+                a = ren.render_view(st, scene, hw[0], hw[1], fov, cull=True)
+                b = ren.render_view(st, scene, hw[0], hw[1], fov, cull=False)
+                assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["depth"], b["depth"])
+                assert np.array_equal(a["mask"], b["mask"])
