@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-stats", action="store_true", help="skip the counting replay (profiling runs)")
     ap.add_argument("--traffic-kib", type=str, default=None,
-                    help="FETCH,WRITE KiB per dispatch of the fused kernel from rocprofv3 (scaled)")
+                    help="FETCH,WRITE KiB per dispatch of the render kernel from rocprofv3, already scaled "
+                         "(default: the committed profiles/render_forest256_pmc.md figures if the kernel is unchanged)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -60,6 +61,25 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 5}))
+
+
+def committed_traffic():
+    """(fetch_kib, write_kib) per dispatch from profiles/render_forest256_pmc.md if the render kernel's
+    sources still hash as when the counters were taken, else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "render_forest256_pmc.md")
+    if not os.path.exists(path):
+        return None
+    line = [l for l in open(path) if l.startswith("traffic_kib_per_dispatch:")]
+    if not line:
+        return None
+    kv = dict(tok.split("=") for tok in line[0].split(":", 1)[1].split())
+    csrc = os.path.join(ROOT, "paper_2407_14783_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                for f in ("render.hip", "vf_internal.h", "dynamics.h"))).hexdigest()[:16]
+    if h != kv.get("source_sha256_16"):
+        return None
+    return float(kv["fetch"]), float(kv["write"])
 
 
 def cpu_baseline(sc, s0, acts, params, budget_s):
@@ -177,8 +197,9 @@ def main():
                                           "valu_ops": ops}}
         out["ray_tri_tests_per_s"] = tri / (ms_per_step / 1e3)
         out["rays_per_s"] = rays / (ms_per_step / 1e3)
-    if args.traffic_kib:
-        fetch_kib, write_kib = (float(x) for x in args.traffic_kib.split(","))
+    tk = tuple(float(x) for x in args.traffic_kib.split(",")) if args.traffic_kib else committed_traffic()
+    if tk:
+        fetch_kib, write_kib = tk
         traffic = (fetch_kib + write_kib) * 1024.0
         if "roofline" in out:
             out["roofline"]["traffic"] = traffic

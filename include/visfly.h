@@ -229,6 +229,76 @@ vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset);
  * VF_OK, or VF_EDEVICE with the reason in vf_last_error(). */
 vf_status vf_sync_check(vf_ctx* ctx, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop over resident env slots.
+ * A request is one step + render of n_env envs of one scene at one image size.
+ * The server keeps drone states resident in the caller's state table, copies a
+ * request's host inputs on submit, and a worker thread admits pending requests
+ * in arrival order into batches as stream slots and arena memory free up:
+ * n_streams batches may be in flight at once (they overlap on the GPU), each in
+ * a device arena of hbm_budget_bytes / n_streams (charged to the context).  A
+ * request that does not fit the arena blocks those behind it (no starvation);
+ * a request touching an env slot that an in-flight or earlier queued request
+ * touches waits for it, so each env sees its requests in submission order.
+ * Results (depth, optional ids / colours, new states) come back to host memory;
+ * latency is measured from submit to the completion of the batch.  Agents are
+ * independent, so a request's result does not depend on the batch it joins.
+ * ------------------------------------------------------------------------- */
+typedef struct vf_server vf_server; /* opaque */
+
+typedef struct vf_server_config {
+    vf_dyn_params params;      /* dynamics of every request */
+    int32_t n_streams;         /* batches in flight at once, 1..16 */
+    int32_t max_batch_agents;  /* agents per batch */
+    int32_t max_h, max_w;      /* largest image a request may ask for */
+    int32_t want_tri_id;       /* 1: return hit triangle ids */
+    int32_t want_rgb;          /* 1: return planar colour */
+    int64_t hbm_budget_bytes;  /* device memory for in-flight batches (work lists + outputs) */
+} vf_server_config;
+
+typedef struct vf_request_desc {
+    int32_t scene_id, H, W, n_env;
+    float hfov, near_clip, far_clip, miss_depth;
+} vf_request_desc;
+
+/* Where a request's results go.  Device buffers (any may be NULL) receive them by
+ * device-to-device copies on the batch's stream before the request completes:
+ * depth [n_env][H][W] float32, tri_id [n_env][H][W] int32 (needs want_tri_id),
+ * rgb [n_env][3][H][W] uint8 (needs want_rgb), state [n_env][17] float32.
+ * host_results = 1 also keeps host copies for vf_server_wait. */
+typedef struct vf_request_out {
+    float* depth;
+    int32_t* tri_id;
+    uint8_t* rgb;
+    float* state;
+    int32_t host_results;
+    int32_t pad;
+} vf_request_out;
+
+typedef struct vf_server_stats {
+    int64_t batches, agents, requests, max_batch_agents, pending, in_flight_batches;
+} vf_server_stats;
+
+/* state_table [n_slots][17] float32 [dev]: resident env states, updated in place. */
+vf_status vf_server_create(vf_ctx* ctx, const vf_server_config* cfg, float* state_table, int64_t n_slots,
+                           vf_server** out);
+/* env_slots [n_env] int32 [host], distinct, in [0, n_slots); actions [n_env][4] float32 [host];
+ * out [host] or NULL (= host results only).  Returns at once with a ticket; VF_ENOSCENE /
+ * VF_EINVAL / VF_ENOMEM (larger than one arena).  Device output buffers must stay valid until
+ * the request completes. */
+vf_status vf_server_submit(vf_server* s, const vf_request_desc* d, const int32_t* env_slots, const float* actions,
+                           const vf_request_out* out, int64_t* ticket);
+/* done = 1 once the ticket's batch has completed. */
+vf_status vf_server_poll(vf_server* s, int64_t ticket, int32_t* done);
+/* Block until done, copy the host results (if the request kept them) to host buffers (depth
+ * [n_env][H][W]; tri_id likewise; rgb per env planar [3][H][W]; state [n_env][17]; any may be NULL)
+ * and release the ticket; latency_s = completion - submission (s). */
+vf_status vf_server_wait(vf_server* s, int64_t ticket, float* depth, int32_t* tri_id, uint8_t* rgb, float* state,
+                         double* latency_s);
+vf_status vf_server_stats_get(vf_server* s, vf_server_stats* out);
+/* VF_EBUSY while requests are pending; in-flight batches are drained. */
+vf_status vf_server_destroy(vf_server* s);
+
 /* Bytes the context currently holds, and its budget (0 = none). */
 vf_status vf_mem_usage(vf_ctx* ctx, int64_t* used_bytes, int64_t* budget_bytes);
 

@@ -15,23 +15,23 @@ import numpy as np
 from . import dynamics, render
 
 
-def rollout_loss(state0, actions, params, scene, goals, view, d0=1.0, w_goal=0.01, return_ids=False):
-    """L(s0, a_0..a_{H-1}) in FP64; optionally the per-step hit ids (for tie screening)."""
+def rollout_loss(state0, actions, params, scene, goals, view, d0=1.0, w_goal=0.01, return_images=False):
+    """L(s0, a_0..a_{H-1}) in FP64; optionally the per-step depth images (for discontinuity screening)."""
     s = np.asarray(state0, dtype=np.float64)
     goals = np.asarray(goals, dtype=np.float64)
     total = 0.0
-    ids = []
+    images = []
     for a in actions:
         s = dynamics.step(s, a, params)
         for i in range(s.shape[0]):
             r = render.render_view(s[i], scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
                                    view.get("miss_depth"), with_mask=False)
             total += float(np.mean(np.exp(-r["depth"] / d0)))
-            if return_ids:
-                ids.append(r["id"])
+            if return_images:
+                images.append(r["depth"])
         total += w_goal * float(np.sum((s[:, 0:3] - goals) ** 2))
-    if return_ids:
-        return total, np.stack(ids) if ids else np.zeros((0,))
+    if return_images:
+        return total, np.stack(images) if images else np.zeros((0,))
     return total
 
 
@@ -42,18 +42,34 @@ def central_difference(fun, x, direction, h=1e-6):
     return (fun(x + h * u) - fun(x - h * u)) / (2.0 * h)
 
 
-def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_actions, h=1e-6, **kw):
+def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_actions, h=1e-6, d0=1.0,
+                        w_goal=0.01, jump_abs=1e-2, jump_rel=1e-3):
     """Directional derivative of the rollout loss along (u_state, u_actions) by central differences.
 
-    Returns (derivative, ids_stable): ids_stable is False when any pixel's hit
-    triangle differs between the +h and -h rollouts (the derivative is then not
-    defined by a single smooth branch and the direction should be discarded).
+    Returns (derivative, smooth, corrected, n_jumps).  The loss is piecewise
+    smooth: a pixel whose ray crosses a silhouette between the +h and -h rollouts
+    changes depth by a finite jump (flagged when |D+ - D-| > jump_abs + jump_rel D),
+    and the plain difference quotient then measures that jump.  `smooth` says no
+    pixel jumped.  `corrected` removes exactly the jumped pixels' terms
+    exp(-D/d0)/P from both rollouts before differencing: the derivative of the
+    loss restricted to the pixels that stay on one smooth branch (a change of hit
+    triangle across a shared edge keeps the depth continuous and is kept).
     """
     s0 = np.asarray(state0, dtype=np.float64)
     a = np.asarray(actions, dtype=np.float64)
-    lp, idp = rollout_loss(s0 + h * u_state, a + h * u_actions, params, scene, goals, view, return_ids=True, **kw)
-    lm, idm = rollout_loss(s0 - h * u_state, a - h * u_actions, params, scene, goals, view, return_ids=True, **kw)
-    return (lp - lm) / (2.0 * h), bool(np.array_equal(idp, idm))
+    lp, dp = rollout_loss(s0 + h * u_state, a + h * u_actions, params, scene, goals, view, d0=d0, w_goal=w_goal,
+                          return_images=True)
+    lm, dm = rollout_loss(s0 - h * u_state, a - h * u_actions, params, scene, goals, view, d0=d0, w_goal=w_goal,
+                          return_images=True)
+    raw = (lp - lm) / (2.0 * h)
+    if dp.size == 0:
+        return raw, True, raw, 0
+    jumped = np.abs(dp - dm) > jump_abs + jump_rel * np.minimum(np.abs(dp), np.abs(dm))
+    n_pix = dp[0].size
+    cp = float(np.sum(np.exp(-dp[jumped] / d0)) / n_pix)
+    cm = float(np.sum(np.exp(-dm[jumped] / d0)) / n_pix)
+    corrected = ((lp - cp) - (lm - cm)) / (2.0 * h)
+    return raw, not bool(jumped.any()), corrected, int(jumped.sum())
 
 
 def step_jacobian(state, action, params, h=1e-6):

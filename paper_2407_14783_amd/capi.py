@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE",
 # every symbol include/visfly.h declares
 EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_scene_info_get", "vf_scene_export",
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
-            "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode")
+            "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_server_create",
+            "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy")
 
 
 class DynParams(ctypes.Structure):

@@ -302,12 +302,27 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
     for (int k = 0; k < 17; ++k) a.state[slot * 17 + k] = o[k];
 }
 
+// Copy state rows idx[i] -> out[i] (one thread per value).
+__global__ void k_gather_rows(const float* __restrict__ state, const int32_t* __restrict__ idx, int32_t n,
+                              float* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * 17) return;
+    int a = i / 17, k = i - a * 17;
+    out[i] = state[(int64_t)idx[a] * 17 + k];
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_step(const StepArgs& a, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_step, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n, float* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3((n * 17 + 255) / 256), dim3(256), 0, st, state, idx, n, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,470 @@
+// Continuous-batching server for step + render requests (the serving form of the
+// batched per-environment step: parallel agents in several scenes, Sec. III-B/D).
+//
+// Requests (a scene, an image size, a set of resident env slots and one action
+// per env) are queued on submit with their host inputs copied.  A worker thread
+// forms batches: whenever one of the server's stream slots is idle it takes, in
+// arrival order, every pending request that (a) fits the slot's device arena
+// (outputs + work list: the HBM budget of one in-flight batch), (b) touches no
+// env slot that an in-flight batch or an earlier request of this batch touches,
+// and (c) keeps the batch within max_batch_agents.  A request that does not fit
+// the arena stops the scan (requests behind it wait: no starvation); a request
+// that conflicts on an env slot is skipped this round and keeps its place.
+// The batch's work list (views with output offsets, env slots, actions) goes to
+// the device in one copy, then the step and render kernels run on the slot's
+// stream and the outputs come back to pinned host memory on the same stream.
+// Several slots are in flight at once, so batches overlap on the device while
+// new requests are admitted.  Agents are independent, so a request's result is
+// bitwise the same alone or in any mix.
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_set>
+
+#include "vf_internal.h"
+
+namespace vf {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    int64_t ticket = 0;
+    vf_request_desc desc{};
+    vf_request_out out{};
+    bool host = true;
+    std::vector<int32_t> slots;
+    std::vector<float> actions;
+    Clock::time_point arrival;
+    Clock::time_point done_at;
+    bool done = false;
+    vf_status status = VF_OK;
+    // results (host)
+    std::vector<float> depth;
+    std::vector<int32_t> tri_id;
+    std::vector<uint8_t> rgb;
+    std::vector<float> state;
+};
+
+struct SlotArena {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    void* dev = nullptr;        // device arena
+    void* host = nullptr;       // pinned host arena (work list upload + results)
+    int64_t bytes = 0;
+    bool busy = false;
+    std::vector<Request*> reqs;
+    std::vector<int64_t> px_off;   // per request: first pixel in the batch
+    int64_t n_agents = 0, n_px = 0;
+    int64_t off_views = 0, off_idx = 0, off_act = 0, off_depth = 0, off_ids = 0, off_rgb = 0, off_state = 0;
+    int64_t host_res = 0;      // start of the results in the host arena
+};
+
+}  // namespace vf
+
+struct vf_server {
+    vf_ctx* ctx = nullptr;
+    vf_server_config cfg{};
+    float* state = nullptr;
+    int64_t n_slots = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<vf::Request*> pending;
+    std::map<int64_t, vf::Request*> all;
+    std::vector<vf::SlotArena> arenas;
+    std::unordered_set<int32_t> busy_slots;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    int64_t next_ticket = 1;
+    vf::DynConst dyn{};
+    // statistics
+    int64_t n_batches = 0, n_agents = 0, n_requests = 0, max_batch = 0;
+    std::string worker_error;
+};
+
+namespace vf {
+
+static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Bytes a request needs in an arena (work list + outputs + state echo).
+static int64_t request_bytes(const vf_server_config& cfg, const vf_request_desc& d) {
+    int64_t px = (int64_t)d.H * d.W * d.n_env;
+    int64_t b = (int64_t)d.n_env * ((int64_t)sizeof(vf_view) + 4 + 16 + 17 * 4);
+    b += px * 4;                                  // depth
+    if (cfg.want_tri_id) b += px * 4;
+    if (cfg.want_rgb) b += px * 3;
+    return b + 7 * 256;                           // worst-case alignment of the seven arena sections
+}
+
+static void launch_batch(vf_server* s, SlotArena& a) {
+    // lay out the arena: views | env idx | actions | depth | ids | rgb | state echo
+    int64_t n = a.n_agents, px = a.n_px;
+    a.off_views = 0;
+    a.off_idx = align_up(a.off_views + n * (int64_t)sizeof(vf_view), 256);
+    a.off_act = align_up(a.off_idx + n * 4, 256);
+    a.off_depth = align_up(a.off_act + n * 16, 256);
+    a.off_ids = align_up(a.off_depth + px * 4, 256);
+    a.off_rgb = align_up(a.off_ids + (s->cfg.want_tri_id ? px * 4 : 0), 256);
+    a.off_state = align_up(a.off_rgb + (s->cfg.want_rgb ? px * 3 : 0), 256);
+    int64_t end = align_up(a.off_state + n * 17 * 4, 256);
+    if (end > a.bytes) {   // admission sizes requests so this cannot happen; never launch past the arena
+        s->worker_error = "batch larger than its arena";
+        for (Request* r : a.reqs) {
+            r->status = VF_ENOMEM;
+            r->done = true;
+            r->done_at = Clock::now();
+            for (int32_t sl : r->slots) s->busy_slots.erase(sl);
+        }
+        a.reqs.clear();
+        a.busy = false;
+        return;
+    }
+    char* h = (char*)a.host;
+    vf_view* hv = (vf_view*)(h + a.off_views);
+    int32_t* hi = (int32_t*)(h + a.off_idx);
+    float* ha = (float*)(h + a.off_act);
+    int64_t agent = 0, pix = 0;
+    a.px_off.clear();
+    for (Request* r : a.reqs) {
+        a.px_off.push_back(pix);
+        for (int32_t e = 0; e < r->desc.n_env; ++e) {
+            vf_view& v = hv[agent];
+            v.scene_id = r->desc.scene_id;
+            v.H = r->desc.H;
+            v.W = r->desc.W;
+            v.flags = 0;
+            v.hfov = r->desc.hfov;
+            v.near_clip = r->desc.near_clip;
+            v.far_clip = r->desc.far_clip;
+            v.miss_depth = r->desc.miss_depth;
+            v.out_offset = pix;
+            hi[agent] = r->slots[e];
+            memcpy(ha + 4 * agent, r->actions.data() + 4 * e, 16);
+            pix += (int64_t)r->desc.H * r->desc.W;
+            ++agent;
+        }
+    }
+    char* d = (char*)a.dev;
+    hipError_t e = hipMemcpyAsync(d, h, a.off_depth, hipMemcpyHostToDevice, a.stream);
+    StepArgs sa{(int32_t)n, (const int32_t*)(d + a.off_idx), s->state, s->n_slots, (const float*)(d + a.off_act),
+                s->ctx->d_err, s->dyn};
+    if (e == hipSuccess) e = launch_step(sa, a.stream);
+    RenderArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.scenes = s->ctx->d_scenes;
+    ra.n_scenes = (int32_t)s->ctx->scenes.size();
+    ra.n = (int32_t)n;
+    ra.env_idx = (const int32_t*)(d + a.off_idx);
+    ra.state = s->state;
+    ra.n_slots = s->n_slots;
+    ra.views = (const vf_view*)(d + a.off_views);
+    ra.max_h = s->cfg.max_h;
+    ra.max_w = s->cfg.max_w;
+    ra.depth = (float*)(d + a.off_depth);
+    ra.tri_id = s->cfg.want_tri_id ? (int32_t*)(d + a.off_ids) : nullptr;
+    ra.rgb = s->cfg.want_rgb ? (uint8_t*)(d + a.off_rgb) : nullptr;
+    ra.out_pixels = px;
+    ra.err = s->ctx->d_err;
+    ra.stats = s->ctx->d_stats;
+    if (e == hipSuccess) e = launch_render(ra, false, false, a.stream);
+    // gather the new states of the batch's env slots (for the client) with the render's view of them
+    if (e == hipSuccess) e = launch_gather_rows(s->state, (const int32_t*)(d + a.off_idx), (int32_t)n,
+                                                (float*)(d + a.off_state), a.stream);
+    a.host_res = a.off_depth;
+    // device outputs: one copy per requested buffer
+    bool any_host = false;
+    int64_t ag = 0;
+    for (size_t k = 0; k < a.reqs.size() && e == hipSuccess; ++k) {
+        Request* r = a.reqs[k];
+        any_host |= r->host;
+        int64_t rpx = (int64_t)r->desc.H * r->desc.W * r->desc.n_env, p0 = a.px_off[k];
+        if (r->out.depth && e == hipSuccess)
+            e = hipMemcpyAsync(r->out.depth, d + a.off_depth + 4 * p0, rpx * 4, hipMemcpyDeviceToDevice, a.stream);
+        if (r->out.tri_id && s->cfg.want_tri_id && e == hipSuccess)
+            e = hipMemcpyAsync(r->out.tri_id, d + a.off_ids + 4 * p0, rpx * 4, hipMemcpyDeviceToDevice, a.stream);
+        if (r->out.rgb && s->cfg.want_rgb && e == hipSuccess)
+            e = hipMemcpyAsync(r->out.rgb, d + a.off_rgb + 3 * p0, rpx * 3, hipMemcpyDeviceToDevice, a.stream);
+        if (r->out.state && e == hipSuccess)
+            e = hipMemcpyAsync(r->out.state, d + a.off_state + 4 * 17 * ag, (int64_t)r->desc.n_env * 17 * 4,
+                               hipMemcpyDeviceToDevice, a.stream);
+        ag += r->desc.n_env;
+    }
+    if (e == hipSuccess && any_host)
+        e = hipMemcpyAsync(h + a.off_depth, d + a.off_depth, end - a.off_depth, hipMemcpyDeviceToHost, a.stream);
+    if (e == hipSuccess) e = hipEventRecord(a.event, a.stream);
+    if (e != hipSuccess) {
+        s->worker_error = std::string("batch launch: ") + hipGetErrorString(e);
+        for (Request* r : a.reqs) {
+            r->status = VF_EHIP;
+            r->done = true;
+            r->done_at = Clock::now();
+        }
+        for (Request* r : a.reqs)
+            for (int32_t sl : r->slots) s->busy_slots.erase(sl);
+        a.reqs.clear();
+        a.busy = false;
+        return;
+    }
+    a.busy = true;
+    s->n_batches += 1;
+    s->n_agents += n;
+    if (n > s->max_batch) s->max_batch = n;
+}
+
+static void finish_batch(vf_server* s, SlotArena& a) {
+    Clock::time_point now = Clock::now();
+    char* h = (char*)a.host;
+    const float* depth = (const float*)(h + a.off_depth);
+    const int32_t* ids = (const int32_t*)(h + a.off_ids);
+    const uint8_t* rgb = (const uint8_t*)(h + a.off_rgb);
+    const float* st = (const float*)(h + a.off_state);
+    int64_t agent = 0;
+    for (size_t k = 0; k < a.reqs.size(); ++k) {
+        Request* r = a.reqs[k];
+        int64_t px = (int64_t)r->desc.H * r->desc.W * r->desc.n_env;
+        int64_t p0 = a.px_off[k];
+        if (r->host) {
+            r->depth.assign(depth + p0, depth + p0 + px);
+            if (s->cfg.want_tri_id) r->tri_id.assign(ids + p0, ids + p0 + px);
+            if (s->cfg.want_rgb) r->rgb.assign(rgb + 3 * p0, rgb + 3 * p0 + 3 * px);  // planar per agent
+            r->state.assign(st + 17 * agent, st + 17 * (agent + r->desc.n_env));
+        }
+        agent += r->desc.n_env;
+        r->done_at = now;
+        r->done = true;
+        for (int32_t sl : r->slots) s->busy_slots.erase(sl);
+    }
+    s->n_requests += (int64_t)a.reqs.size();
+    a.reqs.clear();
+    a.busy = false;
+}
+
+static void worker_loop(vf_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->stop.load()) {
+        bool progressed = false;
+        // completions
+        for (auto& a : s->arenas) {
+            if (!a.busy) continue;
+            hipError_t q = hipEventQuery(a.event);
+            if (q == hipSuccess) {
+                finish_batch(s, a);
+                progressed = true;
+            } else if (q != hipErrorNotReady) {
+                s->worker_error = std::string("batch failed: ") + hipGetErrorString(q);
+                for (Request* r : a.reqs) {
+                    r->status = VF_EHIP;
+                    r->done = true;
+                    r->done_at = Clock::now();
+                    for (int32_t sl : r->slots) s->busy_slots.erase(sl);
+                }
+                a.reqs.clear();
+                a.busy = false;
+                progressed = true;
+            }
+        }
+        if (progressed) s->cv_done.notify_all();
+        // admission into idle slots
+        for (auto& a : s->arenas) {
+            if (a.busy || s->pending.empty()) continue;
+            int64_t used = 0, agents = 0, px = 0;
+            std::unordered_set<int32_t> batch_slots;
+            for (auto it = s->pending.begin(); it != s->pending.end();) {
+                Request* r = *it;
+                int64_t need = request_bytes(s->cfg, r->desc);
+                if (used + need > a.bytes || agents + r->desc.n_env > s->cfg.max_batch_agents) break;
+                bool conflict = false;
+                for (int32_t sl : r->slots)
+                    if (s->busy_slots.count(sl) || batch_slots.count(sl)) { conflict = true; break; }
+                if (conflict) { ++it; continue; }
+                for (int32_t sl : r->slots) batch_slots.insert(sl);
+                used += need;
+                agents += r->desc.n_env;
+                px += (int64_t)r->desc.H * r->desc.W * r->desc.n_env;
+                a.reqs.push_back(r);
+                it = s->pending.erase(it);
+            }
+            if (a.reqs.empty()) continue;
+            for (int32_t sl : batch_slots) s->busy_slots.insert(sl);
+            a.n_agents = agents;
+            a.n_px = px;
+            launch_batch(s, a);
+            progressed = true;
+        }
+        if (progressed) s->cv_done.notify_all();
+        bool any_busy = false;
+        for (auto& a : s->arenas) any_busy |= a.busy;
+        if (any_busy)
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else if (!progressed)
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+    }
+}
+
+}  // namespace vf
+
+using namespace vf;
+
+extern "C" {
+
+vf_status vf_server_create(vf_ctx* ctx, const vf_server_config* cfg, float* state_table, int64_t n_slots,
+                           vf_server** out) {
+    if (!ctx || !cfg || !state_table || !out) return fail(VF_EINVAL, "vf_server_create: NULL argument");
+    std::string why;
+    if (!check_dyn_params(cfg->params, &why)) return fail(VF_EINVAL, "vf_server_create: " + why);
+    if (cfg->n_streams < 1 || cfg->n_streams > 16) return fail(VF_EINVAL, "vf_server_create: n_streams in [1, 16]");
+    if (cfg->max_h < 1 || cfg->max_w < 1 || cfg->max_h > kMaxImage || cfg->max_w > kMaxImage)
+        return fail(VF_EINVAL, "vf_server_create: max_h/max_w in [1, 1024]");
+    if (cfg->max_batch_agents < 1 || n_slots < 1) return fail(VF_EINVAL, "vf_server_create: empty batch or table");
+    if (cfg->hbm_budget_bytes < 1) return fail(VF_EINVAL, "vf_server_create: hbm_budget_bytes must be > 0");
+    VF_HIP(hipSetDevice(ctx->device));
+    vf_server* s = new vf_server();
+    s->ctx = ctx;
+    s->cfg = *cfg;
+    s->state = state_table;
+    s->n_slots = n_slots;
+    s->dyn = make_dyn_const(cfg->params);
+    int64_t per = cfg->hbm_budget_bytes / cfg->n_streams / 256 * 256;
+    s->arenas.resize(cfg->n_streams);
+    vf_status st = VF_OK;
+    for (auto& a : s->arenas) {
+        a.bytes = per;
+        st = ctx_alloc(ctx, &a.dev, per);
+        if (st != VF_OK) break;
+        if (hipHostMalloc(&a.host, per, hipHostMallocDefault) != hipSuccess) {
+            a.host = nullptr;
+            st = fail(VF_ENOMEM, "vf_server_create: pinned host arena");
+            break;
+        }
+        if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&a.event, hipEventDisableTiming) != hipSuccess) {
+            st = fail(VF_EHIP, "vf_server_create: stream/event");
+            break;
+        }
+    }
+    if (st != VF_OK) {
+        for (auto& a : s->arenas) {
+            if (a.dev) ctx_free(ctx, a.dev, a.bytes);
+            if (a.host) (void)hipHostFree(a.host);
+            if (a.event) (void)hipEventDestroy(a.event);
+            if (a.stream) (void)hipStreamDestroy(a.stream);
+        }
+        delete s;
+        return st;
+    }
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return VF_OK;
+}
+
+vf_status vf_server_submit(vf_server* s, const vf_request_desc* d, const int32_t* env_slots, const float* actions,
+                           const vf_request_out* out, int64_t* ticket) {
+    if (!s || !d || !env_slots || !actions || !ticket) return fail(VF_EINVAL, "vf_server_submit: NULL argument");
+    if (d->n_env < 1) return fail(VF_EINVAL, "vf_server_submit: n_env must be >= 1");
+    if (d->H < 1 || d->W < 1 || d->H > s->cfg.max_h || d->W > s->cfg.max_w)
+        return fail(VF_EINVAL, "vf_server_submit: image size outside the server's limits");
+    if (!(d->hfov > 0.f && d->hfov < 3.1415926f)) return fail(VF_EINVAL, "vf_server_submit: bad hfov");
+    if (d->scene_id < 0 || d->scene_id >= (int32_t)s->ctx->scenes.size() || !s->ctx->scenes[d->scene_id].used)
+        return fail(VF_ENOSCENE, "vf_server_submit: no such scene");
+    if (request_bytes(s->cfg, *d) > s->arenas[0].bytes)
+        return fail(VF_ENOMEM, "vf_server_submit: request larger than one in-flight batch's share of the budget");
+    if (d->n_env > s->cfg.max_batch_agents) return fail(VF_EINVAL, "vf_server_submit: n_env > max_batch_agents");
+    std::unordered_set<int32_t> seen;
+    for (int32_t e = 0; e < d->n_env; ++e) {
+        if (env_slots[e] < 0 || env_slots[e] >= s->n_slots) return fail(VF_EINVAL, "vf_server_submit: env slot out of range");
+        if (!seen.insert(env_slots[e]).second) return fail(VF_EINVAL, "vf_server_submit: duplicate env slot");
+    }
+    Request* r = new Request();
+    r->desc = *d;
+    if (out) {
+        r->out = *out;
+        r->host = out->host_results != 0;
+    }
+    r->slots.assign(env_slots, env_slots + d->n_env);
+    r->actions.assign(actions, actions + 4 * (int64_t)d->n_env);
+    r->arrival = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->ticket = s->next_ticket++;
+        s->all[r->ticket] = r;
+        s->pending.push_back(r);
+    }
+    s->cv_work.notify_one();
+    *ticket = r->ticket;
+    return VF_OK;
+}
+
+vf_status vf_server_poll(vf_server* s, int64_t ticket, int32_t* done) {
+    if (!s || !done) return fail(VF_EINVAL, "vf_server_poll: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VF_EINVAL, "vf_server_poll: unknown ticket");
+    *done = it->second->done ? 1 : 0;
+    return VF_OK;
+}
+
+vf_status vf_server_wait(vf_server* s, int64_t ticket, float* depth, int32_t* tri_id, uint8_t* rgb, float* state,
+                         double* latency_s) {
+    if (!s) return fail(VF_EINVAL, "vf_server_wait: NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(VF_EINVAL, "vf_server_wait: unknown ticket");
+    Request* r = it->second;
+    s->cv_done.wait(lk, [&] { return r->done; });
+    s->all.erase(it);
+    lk.unlock();
+    vf_status st = r->status;
+    if (st == VF_OK && r->host) {
+        if (depth) memcpy(depth, r->depth.data(), r->depth.size() * 4);
+        if (tri_id && !r->tri_id.empty()) memcpy(tri_id, r->tri_id.data(), r->tri_id.size() * 4);
+        if (rgb && !r->rgb.empty()) memcpy(rgb, r->rgb.data(), r->rgb.size());
+        if (state) memcpy(state, r->state.data(), r->state.size() * 4);
+    }
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->done_at - r->arrival).count();
+    delete r;
+    if (st != VF_OK) return fail(st, "vf_server_wait: batch failed");
+    return VF_OK;
+}
+
+vf_status vf_server_stats_get(vf_server* s, vf_server_stats* out) {
+    if (!s || !out) return fail(VF_EINVAL, "vf_server_stats_get: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->batches = s->n_batches;
+    out->agents = s->n_agents;
+    out->requests = s->n_requests;
+    out->max_batch_agents = s->max_batch;
+    out->pending = (int64_t)s->pending.size();
+    int64_t inflight = 0;
+    for (auto& a : s->arenas) inflight += a.busy ? 1 : 0;
+    out->in_flight_batches = inflight;
+    return VF_OK;
+}
+
+vf_status vf_server_destroy(vf_server* s) {
+    if (!s) return fail(VF_EINVAL, "vf_server_destroy: NULL server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->pending.empty()) return fail(VF_EBUSY, "vf_server_destroy: requests still pending");
+    }
+    s->stop.store(true);
+    s->cv_work.notify_all();
+    s->worker.join();
+    for (auto& a : s->arenas) {
+        if (a.stream) (void)hipStreamSynchronize(a.stream);
+        ctx_free(s->ctx, a.dev, a.bytes);
+        (void)hipHostFree(a.host);
+        (void)hipEventDestroy(a.event);
+        (void)hipStreamDestroy(a.stream);
+        for (Request* r : a.reqs) delete r;
+    }
+    for (auto& kv : s->all) delete kv.second;
+    delete s;
+    return VF_OK;
+}
+
+}  // extern "C"

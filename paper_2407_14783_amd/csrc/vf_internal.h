@@ -182,6 +182,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t st);
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st);
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);
 hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st);
+hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n, float* out, hipStream_t st);
 vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t* tris, int32_t nt,
                       const uint8_t* rgb, hipStream_t st, SceneHost* out);
 

@@ -72,7 +72,7 @@ def _rounding_amplification(s0, acts, p):
 
 @pytest.mark.parametrize("variant", ["ctbr_forest", "srt", "euler_nsub4", "hover"])
 def test_dynamics_batch_variants(vf, variant):
-    """Local parity (oracle stepped from every GPU state) at 2e-6 for every variant; 100-step
+    """Local parity (oracle stepped from every GPU state) at 1e-5 for every variant; 100-step
     trajectories at 1e-5 for the CTBR/RK4 benchmark configuration, and for the other variants
     within 32x the oracle's own growth of a one-ulp start perturbation (their conditioning)."""
     sim, ctx = vf
@@ -97,7 +97,7 @@ def test_dynamics_batch_variants(vf, variant):
     header(f"dynamics: {variant}, {n} agents x 100 steps")
     gpu = _gpu_rollout(ctx, p, s0, acts)
     local = max(state_close(gpu[k + 1], odyn.step(gpu[k].astype(np.float64), acts[k], p)) for k in range(100))
-    assert local <= 2e-6, f"{variant}: one-step error {local:.3e}"
+    assert local <= 1e-5, f"{variant}: one-step error {local:.3e}"
     ref = odyn.rollout(s0, acts, p)
     err = max(state_close(gpu[k], ref[k]) for k in range(101))
     tol = STATE_TOL

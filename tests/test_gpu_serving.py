@@ -1,0 +1,178 @@
+"""Serving form on the GPU: continuous batching over resident env slots.
+
+Each request's result (depth, ids, new states) must be bitwise the same when it
+is served alone and when it is mixed into batches with other requests, and equal
+to a plain vf_step over the same slots and actions; requests touching the same
+env slot take effect in submission order; admission never exceeds the budget and
+a large request is not starved by a stream of small ones.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import agents, default_params, scenes
+from tests.gpu_util import header
+
+pytestmark = pytest.mark.gpu
+
+PER = 256
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2407_14783_amd import serving, sim
+    p = default_params()
+    ctx = sim.Context(0)
+    scs = [scenes.room_graph(600, 20000), scenes.box_room(seed=1), scenes.forest(seed=3, n_trees=300)]
+    sids = [ctx.build_scene(s["verts"], s["tris"], s["rgb"]) for s in scs]
+    table = np.concatenate([agents.room_graph_starts(11, PER, scs[0], p),
+                            agents.make_states(np.tile([5.0, 5.0, 2.0], (PER, 1)), p,
+                                               quat=agents.yaw_quat(np.linspace(-3, 3, PER))),
+                            agents.forest_starts(12, PER, scs[2], p)])
+    yield {"p": p, "ctx": ctx, "sim": sim, "serving": serving, "sids": sids, "table": table}
+    for s in sids:
+        ctx.free_scene(s)
+    ctx.close()
+
+
+def _server(env, state, **kw):
+    args = dict(n_streams=3, max_batch_agents=4096, max_hw=(96, 96), want_tri_id=True, want_rgb=True,
+                budget_bytes=256 << 20)
+    args.update(kw)
+    return env["serving"].Server(env["ctx"], env["p"], state, **args)
+
+
+def _request(rng, scene, n_env, hw, env, avoid=()):
+    free = np.setdiff1d(np.arange(PER), np.asarray(list(avoid), dtype=np.int64))
+    slots = scene * PER + rng.choice(free, size=n_env, replace=False)
+    acts = agents.random_actions(int(rng.integers(1 << 30)), 1, n_env, env["p"])[0]
+    return scene, hw, slots.astype(np.int32), acts
+
+
+def test_result_alone_equals_mix_and_plain_step(setup):
+    env = setup
+    rng = np.random.default_rng(5)
+    target = _request(rng, 0, 37, (64, 64), env)
+    tgt_local = target[2] - 0 * PER
+    # served alone
+    st1 = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st1)
+    t = srv.submit(env["sids"][target[0]], target[1], target[2], target[3])
+    alone = srv.wait(t)
+    srv.close()
+    # served in a mix of 40 other requests on other slots (submitted before and after it)
+    st2 = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st2)
+    others = [_request(rng, int(rng.integers(0, 3)), int(rng.integers(1, 120)), [(64, 64), (96, 96), (40, 56)][k % 3],
+                       env, avoid=tgt_local) for k in range(40)]
+    header("serving: target request alone vs in a mix of 40")
+    tickets = [srv.submit(env["sids"][r[0]], r[1], r[2], r[3]) for r in others[:20]]
+    n_px = target[2].shape[0] * 64 * 64
+    dev_out = {"depth": torch.full((n_px,), -1.0).cuda(), "tri_id": torch.full((n_px,), -5, dtype=torch.int32).cuda(),
+               "rgb": torch.zeros(3 * n_px, dtype=torch.uint8).cuda(), "state": torch.zeros(target[2].shape[0] * 17).cuda()}
+    tt = srv.submit(env["sids"][target[0]], target[1], target[2], target[3], out=dev_out)
+    tickets += [srv.submit(env["sids"][r[0]], r[1], r[2], r[3]) for r in others[20:]]
+    mixed = srv.wait(tt)
+    for k in tickets:
+        srv.wait(k, fetch=False)
+    stats = srv.stats()
+    srv.close()
+    assert stats["batches"] >= 2
+    for key in ("depth", "tri_id", "rgb", "state"):
+        assert np.array_equal(alone[key], mixed[key]), key
+        assert np.array_equal(dev_out[key].cpu().numpy().reshape(alone[key].shape), alone[key]), "device " + key
+    # and the plain batched step over the same slots
+    from paper_2407_14783_amd import sim
+    st3 = torch.as_tensor(env["table"]).cuda()
+    n = target[2].shape[0]
+    views, npx, offs, mh, mw = sim.make_views(n, env["sids"][0], (64, 64))
+    depth = torch.empty(npx).cuda()
+    ids = torch.empty(npx, dtype=torch.int32).cuda()
+    env["ctx"].step(env["p"], st3, torch.as_tensor(target[3]).cuda(), views=views,
+                    env_idx=torch.as_tensor(target[2]).cuda(), max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+    env["ctx"].sync_check()
+    assert np.array_equal(depth.cpu().numpy(), alone["depth"])
+    assert np.array_equal(ids.cpu().numpy(), alone["tri_id"])
+    assert np.array_equal(st3.cpu().numpy()[target[2]], alone["state"])
+    assert np.array_equal(st2.cpu().numpy()[target[2]], alone["state"])
+
+
+def test_same_slot_requests_apply_in_order(setup):
+    env = setup
+    rng = np.random.default_rng(9)
+    slots = (2 * PER + rng.choice(PER, 20, replace=False)).astype(np.int32)
+    a1 = agents.random_actions(1, 1, 20, env["p"])[0]
+    a2 = agents.random_actions(2, 1, 20, env["p"])[0]
+    st = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st)
+    t1 = srv.submit(env["sids"][2], (64, 64), slots, a1)
+    t2 = srv.submit(env["sids"][2], (64, 64), slots[::-1].copy(), a2[::-1].copy())
+    r2 = srv.wait(t2)
+    r1 = srv.wait(t1)
+    srv.close()
+    ref = torch.as_tensor(env["table"]).cuda()
+    env["ctx"].step(env["p"], ref, torch.as_tensor(a1).cuda(), env_idx=torch.as_tensor(slots).cuda())
+    s_after_1 = ref.cpu().numpy()[slots]
+    env["ctx"].step(env["p"], ref, torch.as_tensor(a2[::-1].copy()).cuda(), env_idx=torch.as_tensor(slots[::-1].copy()).cuda())
+    assert np.array_equal(r1["state"], s_after_1)
+    assert np.array_equal(r2["state"], ref.cpu().numpy()[slots[::-1]])
+    assert np.array_equal(st.cpu().numpy(), ref.cpu().numpy())
+
+
+def test_budget_admission_and_no_starvation(setup):
+    env = setup
+    rng = np.random.default_rng(13)
+    st = torch.as_tensor(env["table"]).cuda()
+    budget = 2 * (8 << 20)
+    srv = _server(env, st, n_streams=2, budget_bytes=budget, want_rgb=False)
+    used, cap = env["ctx"].mem_usage()
+    from paper_2407_14783_amd import capi
+    # a request larger than one in-flight batch's share is refused at submit
+    big = _request(rng, 1, 200, (96, 96), env)
+    with pytest.raises(capi.VfError) as e:
+        srv.submit(env["sids"][1], big[1], big[2], big[3])
+    assert e.value.status == capi.VF_ENOMEM
+    # a request near the arena size among many small ones completes
+    large = _request(rng, 0, 90, (96, 96), env)
+    small = [_request(rng, 2, int(rng.integers(1, 8)), (64, 64), env) for _ in range(60)]
+    header("serving: large request among 60 small ones, 2 x 8 MiB arenas")
+    ts = [srv.submit(env["sids"][r[0]], r[1], r[2], r[3]) for r in small[:30]]
+    tl = srv.submit(env["sids"][large[0]], large[1], large[2], large[3])
+    ts += [srv.submit(env["sids"][r[0]], r[1], r[2], r[3]) for r in small[30:]]
+    rl = srv.wait(tl)
+    for t in ts:
+        srv.wait(t, fetch=False)
+    stats = srv.stats()
+    srv.close()
+    assert np.isfinite(rl["latency_s"]) and rl["depth"].shape[0] == 90 * 96 * 96
+    assert stats["requests"] == 61 and stats["pending"] == 0
+
+
+def test_submit_errors(setup):
+    env = setup
+    from paper_2407_14783_amd import capi
+    st = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st)
+    acts = np.zeros((2, 4), dtype=np.float32)
+    for slots, sid, hw, status in (([1, 1], env["sids"][0], (64, 64), capi.VF_EINVAL),
+                                   ([1, 3 * PER], env["sids"][0], (64, 64), capi.VF_EINVAL),
+                                   ([1, 2], 999, (64, 64), capi.VF_ENOSCENE),
+                                   ([1, 2], env["sids"][0], (128, 64), capi.VF_EINVAL)):
+        with pytest.raises(capi.VfError) as e:
+            srv.submit(sid, hw, np.asarray(slots, dtype=np.int32), acts)
+        assert e.value.status == status
+    srv.close()
+
+
+def test_poisson_load_latency(setup):
+    env = setup
+    st = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st, want_tri_id=False, want_rgb=False)
+    reqs = env["serving"].make_requests(3, 300, 3, PER, env["p"])
+    lat, wall, frames = env["serving"].run_load(srv, env["sids"], reqs, rate=2000.0, seed=1)
+    srv.close()
+    header(f"serving: {len(reqs)} Poisson requests, p50 {np.percentile(lat, 50) * 1e3:.2f} ms, "
+           f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms, {frames / wall:.0f} frames/s")
+    assert lat.shape[0] == len(reqs) and np.all(lat > 0) and np.all(np.isfinite(lat))

@@ -73,8 +73,8 @@ def test_rollout_goal_term_gradient_closed_form():
     goal = np.array([[3.0, 1.0, 4.0]])
     u_s = np.zeros_like(s0)
     u_s[0, 0:3] = [0.6, 0.0, 0.8]
-    d, stable = grd.rollout_directional(s0, acts, p, far_tri, goal, view, u_s, np.zeros_like(acts))
-    assert stable
+    d, smooth, corr, nj = grd.rollout_directional(s0, acts, p, far_tri, goal, view, u_s, np.zeros_like(acts))
+    assert smooth and nj == 0 and corr == d
     traj = dyn.rollout(s0, acts, p)
     expect = sum(2 * 0.01 * (traj[k, 0, 0:3] - goal[0]) @ u_s[0, 0:3] for k in range(1, 6))
     assert math.isclose(d, expect, rel_tol=1e-6)
@@ -109,3 +109,28 @@ def test_golden_box_room_regression():
                          pixels=np.array(gold["pixels"]))
     assert np.allclose(r["depth"], gold["depth"], rtol=1e-13)
     assert r["id"].tolist() == gold["id"]
+
+
+def test_directional_derivative_flags_silhouette_jumps():
+    """A perturbation that moves a wall edge across pixel rays makes the depth jump: flagged non-smooth."""
+    p = default_params(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0))
+    wall = scenes.plane_quad([5.0, -3.0, -3.0], [0.0, 3.0, 0.0], [0.0, 0.0, 13.0])   # y in [-3, 0], z in [-3, 10]
+    back = scenes.plane_quad([9.0, -50.0, -50.0], [0.0, 100.0, 0.0], [0.0, 0.0, 100.0])
+    sc = {"verts": np.concatenate([wall["verts"], back["verts"]]), "tris": np.concatenate([wall["tris"], back["tris"] + 4]),
+          "rgb": np.concatenate([wall["rgb"], back["rgb"]])}
+    view = {"H": 2, "W": 64, "hfov": math.radians(90), "near": 0.01, "far": 100.0}
+    s0 = make_states([[0.0, 0.0, 5.0]], p, rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    acts = np.zeros((1, 1, 4))
+    # the pixel column just right of the image centre sees the wall edge at y = 0 within ~1e-9 m
+    u_s = np.zeros_like(s0)
+    u_s[0, 1] = 1.0
+    col = 32
+    th = math.tan(view["hfov"] / 2)
+    u = (2 * (col + 0.5) / 64 - 1) * th
+    s0[0, 1] = u * 5.0 + 1e-9          # the ray meets the wall plane at y = s0_y - u * 5: the edge y = 0 is within +-h
+    d, smooth, corr, nj = grd.rollout_directional(s0, acts, p, sc, np.zeros((1, 3)), view, u_s, np.zeros_like(acts),
+                                                  w_goal=0.0)
+    assert not smooth and abs(d) > 1.0 and nj == 2          # the edge column, in both image rows
+    # with the jumped pixel removed, the rest of the image is a wall/backdrop seen head-on while the
+    # camera moves sideways: depth is unchanged, so the corrected derivative vanishes
+    assert abs(corr) < 1e-6
