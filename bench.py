@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-stats", action="store_true", help="skip the counting replay (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the box-room latency, multi-scene and differentiable measurements")
     ap.add_argument("--traffic-kib", type=str, default=None,
                     help="FETCH,WRITE KiB per dispatch of the render kernel from rocprofv3, already scaled "
                          "(default: the committed profiles/render_forest256_pmc.md figures if the kernel is unchanged)")
@@ -110,6 +112,113 @@ def cpu_baseline(sc, s0, acts, params, budget_s):
 def serving_summary(ctx, sim, params):
     from paper_2407_14783_amd import serving
     return serving.bench_summary(ctx, params)
+
+
+def box_room_latency(ctx, sim, params, steps=100):
+    """Single agent in the 192-triangle box room: latency-bound step + render (us per step)."""
+    import torch
+    from workloads import agents, scenes
+    sc = scenes.box_room(seed=1)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    s = torch.as_tensor(agents.box_room_start(params)).cuda()
+    acts = torch.as_tensor(agents.random_actions(2, steps, 1, params)).cuda()
+    views, npx, offs, mh, mw = sim.make_views(1, sid, (64, 64))
+    depth = torch.empty(npx, device="cuda")
+    p = sim.capi.params_struct(params)
+    out = {}
+    for mode, fused in (("split", False), ("fused", True)):
+        ctx.set_launch_mode(fused)
+        for k in range(10):
+            ctx.step(p, s, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            ctx.step(p, s, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{mode}_us_per_step"] = e0.elapsed_time(e1) / steps * 1e3
+    ctx.set_launch_mode(None)
+    ctx.sync_check()
+    ctx.free_scene(sid)
+    return {"workload": "box-room: 1 agent, 192 triangles, 64x64 depth, 100 steps", **out,
+            "frames_per_s": 1e6 / min(out["split_us_per_step"], out["fused_us_per_step"])}
+
+
+def multi_scene_throughput(ctx, sim, params, steps=20):
+    """4,096 agents over the 8 room-graph scenes (Dirichlet split), half 64x64 and half 128x128 depth."""
+    import torch
+    from workloads import agents, scenes
+    scs = scenes.multi_scene_set(seed=6)
+    t0 = time.perf_counter()
+    sids = [ctx.build_scene(s["verts"], s["tris"], s["rgb"]) for s in scs]
+    build_s = time.perf_counter() - t0
+    counts = agents.multi_scene_split(6, 4096, 8)
+    st = np.concatenate([agents.room_graph_starts(60 + j, int(c), scs[j], params) for j, c in enumerate(counts)])
+    scene_of = np.repeat(np.arange(8), counts)
+    rng = np.random.default_rng(6)
+    big = rng.permutation(4096) < 2048
+    hw = np.where(big, 128, 64)
+    views, npx, offs, mh, mw = sim.make_views(4096, np.asarray(sids)[scene_of], np.stack([hw, hw], 1))
+    state = torch.as_tensor(st).cuda()
+    acts = torch.as_tensor(agents.random_actions(6, steps, 4096, params)).cuda()
+    depth = torch.empty(npx, device="cuda")
+    p = sim.capi.params_struct(params)
+    for k in range(3):
+        ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ms = e0.elapsed_time(e1) / steps
+    infos = [ctx.scene_info(s) for s in sids]
+    for s in sids:
+        ctx.free_scene(s)
+    return {"workload": "multi-scene: 4,096 agents over 8 room graphs (20k-2M triangles), half 64x64 half 128x128",
+            "ms_per_step": ms, "frames_per_s": 4096 / (ms / 1e3), "rays_per_s": npx / (ms / 1e3),
+            "frames_64x64_equivalent_per_s": npx / 4096 / (ms / 1e3),
+            "scene_triangles": [int(i["n_tris"]) for i in infos],
+            "scene_build_device_ms": [round(float(i["build_ms"]), 2) for i in infos],
+            "scene_build_wall_s_incl_upload": build_s}
+
+
+def bptt_throughput(ctx, sim, params, n=1024, horizon=64, k=8):
+    """Differentiable rollout: 1,024 agents in the forest, horizon 64, checkpoints every 8, depth loss."""
+    import torch
+    from paper_2407_14783_amd import autograd as vag
+    from workloads import agents, scenes
+    sc = scenes.forest(seed=3)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    s0 = torch.as_tensor(agents.forest_starts(8, n, sc, params)).cuda().requires_grad_(True)
+    rng = np.random.default_rng(8)
+    a = np.concatenate([rng.uniform(0.9, 1.15, (horizon, n, 1)) * params["g"],
+                        rng.uniform(-0.6, 0.6, (horizon, n, 3))], axis=2).astype(np.float32)
+    acts = torch.as_tensor(a).cuda().requires_grad_(True)
+    goals = s0.detach()[:, 0:3] + 10.0
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+
+    def once():
+        states, depths = vag.rollout(ctx, params, s0, acts, views, (mh, mw), npx, checkpoint_every=k)
+        loss = torch.exp(-depths).view(horizon, n, -1).mean(2).sum() + 0.01 * ((states[:, :, 0:3] - goals) ** 2).sum()
+        loss.backward()
+        return loss
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        s0.grad = None
+        acts.grad = None
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.free_scene(sid)
+    return {"workload": "differentiable: 1,024 agents, forest, horizon 64, checkpoints every 8, 64x64 depth loss",
+            "s_per_rollout_fwd_bwd": dt, "agent_steps_per_s": n * horizon / dt}
 
 
 def main():
@@ -206,10 +315,11 @@ def main():
         out["hbm"] = {"bytes_per_launch": traffic, "achieved_GBps": traffic / (ms_per_step / 1e3) / 1e9,
                       "peak_GBps": HBM_PEAK_GBPS, "frac": traffic / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBPS}
     if not args.no_serving:
-        try:
-            out["serving"] = serving_summary(ctx, sim, params)
-        except ImportError:
-            out["serving"] = None
+        out["serving"] = serving_summary(ctx, sim, params)
+    if not args.no_extra:
+        out["box_room_latency"] = box_room_latency(ctx, sim, params)
+        out["multi_scene"] = multi_scene_throughput(ctx, sim, params)
+        out["differentiable"] = bptt_throughput(ctx, sim, params)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, s0, acts_np, params, args.cpu_seconds)
     ctx.free_scene(sid)

@@ -204,14 +204,27 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
                              int32_t max_h, int32_t max_w, const int32_t* tri_id, const float* grad_depth,
                              int64_t out_pixels, float* grad_state, void* stream);
 
-/* How vf_step with views launches its work.  VF_LAUNCH_SPLIT (the default):
- * a dynamics kernel (one thread per agent) then the render kernel, two
- * launches on the stream.  VF_LAUNCH_FUSED: one kernel in which every render
- * workgroup advances its agent's dynamics in one lane and the last workgroup
- * of the agent to finish writes the new state.  Both give bitwise identical
- * states and images; the split form keeps the render kernel at its lower
- * register count and is faster for batches that fill the GPU. */
-enum { VF_LAUNCH_SPLIT = 0, VF_LAUNCH_FUSED = 1 };
+/* Nearest obstacle point (Sec. III-B: the spatial distance module that reports the
+ * relative position of the nearest obstacle point without a collision having to
+ * happen).  For each query point p_i [n][3] float32 [dev] in scene scene_ids[i]
+ * (int32 [dev]) or, if scene_ids is NULL, in scene_id0: the Euclidean distance
+ * to the closest point of any triangle, dist [n] float32 [dev, out], that point
+ * closest [n][3] float32 [dev, out, nullable] and its caller triangle index
+ * tri_id [n] int32 [dev, out, nullable].  Points farther than max_dist from every
+ * triangle give dist = +inf, tri_id = -1.  Equal distances go to the lower index. */
+vf_status vf_closest_point(vf_ctx* ctx, int64_t n, const float* points, const int32_t* scene_ids, int32_t scene_id0,
+                           float max_dist, float* dist, float* closest, int32_t* tri_id, void* stream);
+
+/* How vf_step with views launches its work.  VF_LAUNCH_SPLIT: a dynamics
+ * kernel (one thread per agent) then the render kernel, two launches on the
+ * stream.  VF_LAUNCH_FUSED: one kernel in which every render workgroup advances
+ * its agent's dynamics in one lane and the last workgroup of the agent to finish
+ * writes the new state.  Both give bitwise identical states and images.  The
+ * split form keeps the render kernel at its lower register count and is faster
+ * for batches that fill the GPU; the fused form saves a launch and wins for
+ * small, latency-bound batches.  VF_LAUNCH_AUTO (the default) picks fused when
+ * the render grid has at most 1,024 workgroups (16 agents at 64x64), else split. */
+enum { VF_LAUNCH_SPLIT = 0, VF_LAUNCH_FUSED = 1, VF_LAUNCH_AUTO = 2 };
 vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode);
 
 /* Enable (1) / disable (0) traversal statistics: while enabled, vf_step and

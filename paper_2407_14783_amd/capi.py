@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libvisfly_hip.so")
 VF_OK, VF_EINVAL, VF_ENOMEM, VF_ENOSCENE, VF_EHIP, VF_EBUSY, VF_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 VF_RK4, VF_EULER = 0, 1
 VF_CTBR, VF_SRT = 0, 1
-VF_LAUNCH_SPLIT, VF_LAUNCH_FUSED = 0, 1
+VF_LAUNCH_SPLIT, VF_LAUNCH_FUSED, VF_LAUNCH_AUTO = 0, 1, 2
 STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE", -4: "VF_EHIP", -5: "VF_EBUSY",
                 -6: "VF_EDEVICE"}
 
@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE",
 EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_scene_info_get", "vf_scene_export",
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
             "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_server_create",
-            "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy")
+            "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
+            "vf_closest_point")
 
 
 class DynParams(ctypes.Structure):
@@ -76,6 +77,7 @@ def _load():
         "vf_render_backward": ([P, I64, P, P, I32, I32, P, P, I64, P, P], I32),
         "vf_set_stats": ([P, I32], I32),
         "vf_set_launch_mode": ([P, I32], I32),
+        "vf_closest_point": ([P, I64, P, P, I32, ctypes.c_float, P, P, P, P], I32),
         "vf_stats_read": ([P, ctypes.POINTER(U64), I32], I32),
         "vf_sync_check": ([P, P], I32),
         "vf_mem_usage": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),

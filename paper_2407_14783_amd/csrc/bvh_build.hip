@@ -525,7 +525,8 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     // scene block: nodes | tris | sorted_of | rgb
     const int64_t max_nodes = nt > 1 ? nt : 1;
     int64_t node_bytes = max_nodes * (int64_t)sizeof(Node4);
-    int64_t tri_bytes = (int64_t)nt * (int64_t)sizeof(Tri);
+    // padded by kLeafMax records: a leaf's triangles are fetched as one fixed-size burst
+    int64_t tri_bytes = ((int64_t)nt + kLeafMax) * (int64_t)sizeof(Tri);
     int64_t map_bytes = ((int64_t)nt * 4 + 255) / 256 * 256;
     int64_t rgb_bytes = ((int64_t)nt * 3 + 255) / 256 * 256;
     Node4* nodes = nullptr;
@@ -581,6 +582,8 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     int32_t* sorted_of = (int32_t*)((char*)block + node_bytes + tri_bytes);
     uint8_t* rgb_out = (uint8_t*)((char*)block + node_bytes + tri_bytes + map_bytes);
     hipError_t e = hipMemcpyAsync(nodes, tmp_nodes, node_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemsetAsync((char*)tri_out + (int64_t)nt * sizeof(Tri), 0, kLeafMax * sizeof(Tri), st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_tri_write, dim3(blocks_for(nt, 256)), dim3(256), 0, st, verts, tris, va, nt, nv, tri_out,
                            sorted_of);

@@ -130,22 +130,27 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
                 }
             }
         } else {
-            // leaf: entry = -((first << 3 | (count - 1)) + 1)
+            // leaf: entry = -((first << 3 | (count - 1)) + 1).  All kLeafMax records are fetched in
+            // one burst of scalar loads (the triangle array is padded by kLeafMax records), then the
+            // leaf's own triangles are tested from registers.
             int32_t code = -entry - 1;
             int32_t first = code >> 3, cnt = (code & 7) + 1;
-            for (int j = 0; j < cnt; ++j) {
-                const uint32_t CONST_AS* tp = (const uint32_t CONST_AS*)(tris + first + j);
-                uint32_t tw[12];
+            const uint32_t CONST_AS* tp = (const uint32_t CONST_AS*)(tris + first);
+            uint32_t tw[12 * kLeafMax];
 #pragma unroll
-                for (int i = 0; i < 12; ++i) tw[i] = tp[i];
-                const float v0x = __uint_as_float(tw[0]), v0y = __uint_as_float(tw[1]), v0z = __uint_as_float(tw[2]);
-                const int32_t id = (int32_t)tw[3];
-                const float e1x = __uint_as_float(tw[4]), e1y = __uint_as_float(tw[5]), e1z = __uint_as_float(tw[6]);
-                const float e2x = __uint_as_float(tw[8]), e2y = __uint_as_float(tw[9]), e2z = __uint_as_float(tw[10]);
-                if (STATS) {
-                    ts.tri_wave += 1;
-                    ts.tri_lane += valid ? 1 : 0;
-                }
+            for (int i = 0; i < 12 * kLeafMax; ++i) tw[i] = tp[i];
+            if (STATS) {
+                ts.tri_wave += cnt;
+                ts.tri_lane += valid ? cnt : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kLeafMax; ++j) {
+                if (j >= cnt) break;
+                const uint32_t* w3 = tw + 12 * j;
+                const float v0x = __uint_as_float(w3[0]), v0y = __uint_as_float(w3[1]), v0z = __uint_as_float(w3[2]);
+                const int32_t id = (int32_t)w3[3];
+                const float e1x = __uint_as_float(w3[4]), e1y = __uint_as_float(w3[5]), e1z = __uint_as_float(w3[6]);
+                const float e2x = __uint_as_float(w3[8]), e2y = __uint_as_float(w3[9]), e2z = __uint_as_float(w3[10]);
                 float px = d[1] * e2z - d[2] * e2y;
                 float py = d[2] * e2x - d[0] * e2z;
                 float pz = d[0] * e2y - d[1] * e2x;
@@ -160,10 +165,8 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
                 float t = (e2x * qx + e2y * qy + e2z * qz) * inv_det;
                 bool h = valid && det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t >= t_near;
                 bool take = h && (t < t_best || (t == t_best && (id_best < 0 || id < id_best)));
-                if (take) {
-                    t_best = t;
-                    id_best = id;
-                }
+                t_best = take ? t : t_best;
+                id_best = take ? id : id_best;
             }
         }
         if (sp == 0) break;

@@ -313,7 +313,13 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     }
     RenderArgs a = make_render_args(ctx, n, env_idx, state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
                                     out_pixels);
-    if (ctx->launch_mode == VF_LAUNCH_SPLIT) {
+    bool split = ctx->launch_mode == VF_LAUNCH_SPLIT;
+    if (ctx->launch_mode == VF_LAUNCH_AUTO) {
+        int64_t tiles = (int64_t)((max_h + kTile - 1) / kTile) * ((max_w + kTile - 1) / kTile);
+        int64_t groups = n * ((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+        split = groups > 1024;
+    }
+    if (split) {
         StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
         VF_HIP(launch_step(sa, st));
         VF_HIP(launch_render(a, false, ctx->stats, st));
@@ -376,9 +382,26 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
     return VF_OK;
 }
 
+vf_status vf_closest_point(vf_ctx* ctx, int64_t n, const float* points, const int32_t* scene_ids, int32_t scene_id0,
+                           float max_dist, float* dist, float* closest, int32_t* tri_id, void* stream) {
+    if (!ctx) return fail(VF_EINVAL, "vf_closest_point: NULL context");
+    if (n < 0 || n > (1 << 26)) return fail(VF_EINVAL, "vf_closest_point: n must be in [0, 2^26]");
+    if (n > 0 && (!points || !dist)) return fail(VF_EINVAL, "vf_closest_point: NULL array");
+    if (!(max_dist > 0.0f)) return fail(VF_EINVAL, "vf_closest_point: max_dist must be > 0");
+    if (!scene_ids && (scene_id0 < 0 || scene_id0 >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id0].used))
+        return fail(VF_ENOSCENE, "vf_closest_point: no such scene");
+    if (n == 0) return VF_OK;
+    VF_HIP(hipSetDevice(ctx->device));
+    QueryArgs q{ctx->d_scenes, (int32_t)ctx->scenes.size(), (int32_t)n, points, scene_ids, scene_id0, max_dist, dist,
+                closest, tri_id, ctx->d_err};
+    VF_HIP(launch_closest_point(q, (hipStream_t)stream));
+    return VF_OK;
+}
+
 vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode) {
     if (!ctx) return fail(VF_EINVAL, "vf_set_launch_mode: NULL context");
-    if (mode != VF_LAUNCH_SPLIT && mode != VF_LAUNCH_FUSED) return fail(VF_EINVAL, "vf_set_launch_mode: bad mode");
+    if (mode != VF_LAUNCH_SPLIT && mode != VF_LAUNCH_FUSED && mode != VF_LAUNCH_AUTO)
+        return fail(VF_EINVAL, "vf_set_launch_mode: bad mode");
     ctx->launch_mode = mode;
     return VF_OK;
 }

@@ -19,7 +19,10 @@ namespace vf {
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
 constexpr int kWavesPerBlock = 4;     // render workgroup = 4 wavefronts = 4 tiles
-constexpr int kLeafMax = 4;           // triangles per BVH leaf
+#ifndef VF_LEAF_MAX
+#define VF_LEAF_MAX 4
+#endif
+constexpr int kLeafMax = VF_LEAF_MAX;  // triangles per BVH leaf (at most 8: the stack entry keeps 3 bits)
 constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
 constexpr int kMaxBvhDepth = 40;      // builds deeper than this are rejected (3 pushes per level)
 constexpr int kMaxScenes = 1024;
@@ -118,7 +121,7 @@ struct vf_ctx {
     uint32_t* d_err = nullptr;             // sticky error word
     unsigned long long* d_stats = nullptr; // 8 counters
     bool stats = false;
-    int32_t launch_mode = VF_LAUNCH_SPLIT;
+    int32_t launch_mode = VF_LAUNCH_AUTO;
     std::vector<vf::Counters> counters;
 };
 
@@ -178,6 +181,20 @@ struct RenderBackArgs {
     float* grad_state;
     uint32_t* err;
 };
+struct QueryArgs {
+    const SceneDesc* scenes;
+    int32_t n_scenes;
+    int32_t n;
+    const float* points;
+    const int32_t* scene_ids;
+    int32_t scene_id0;
+    float max_dist;
+    float* dist;
+    float* closest;
+    int32_t* tri_id;
+    uint32_t* err;
+};
+hipError_t launch_closest_point(const QueryArgs& q, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, hipStream_t st);
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st);
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);

@@ -148,13 +148,26 @@ class Context:
                                      int(max_hw[1]), _ptr(tri_id), _ptr(grad_depth), int(out_pixels),
                                      _ptr(grad_state), _stream(stream)), "vf_render_backward")
 
+    def closest_point(self, points, scene_id, max_dist=1e30, closest=None, tri_id=None, stream=None):
+        """Distance [n] from each point [n, 3] (device) to the nearest triangle of scene_id (an int or a
+        device int32 tensor [n] of per-point scenes)."""
+        n = points.shape[0]
+        _check_rows(points, n, 3, "points")
+        dist = torch.empty(n, dtype=torch.float32, device=points.device)
+        ids_t = scene_id if torch.is_tensor(scene_id) else None
+        sid0 = 0 if ids_t is not None else int(scene_id)
+        check(lib.vf_closest_point(self.h, n, _ptr(points), _ptr(ids_t), sid0, float(max_dist), _ptr(dist),
+                                   _ptr(closest), _ptr(tri_id), _stream(stream)), "vf_closest_point")
+        return dist
+
     # ---------------------------------------------------------------- diagnostics
     def sync_check(self, stream=None):
         check(lib.vf_sync_check(self.h, _stream(stream)), "vf_sync_check")
 
     def set_launch_mode(self, fused):
-        check(lib.vf_set_launch_mode(self.h, capi.VF_LAUNCH_FUSED if fused else capi.VF_LAUNCH_SPLIT),
-              "vf_set_launch_mode")
+        """True: fused single launch; False: split; None: automatic by batch size (the default)."""
+        mode = capi.VF_LAUNCH_AUTO if fused is None else (capi.VF_LAUNCH_FUSED if fused else capi.VF_LAUNCH_SPLIT)
+        check(lib.vf_set_launch_mode(self.h, mode), "vf_set_launch_mode")
 
     def set_stats(self, on):
         check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")
