@@ -1,14 +1,16 @@
 """Benchmark of the batched quadrotor step + ray-cast render on one MI355X.
 
-A step is one fused vf_step launch over the whole batch: CTBR controller, rotor
-lag, RK4 (Sec. III-A) and the 64x64 depth / triangle id / colour render of every
-agent at its new pose (Sec. III-B), on synthetic inputs resident in HBM.
+A step is one vf_step call over the whole batch: CTBR controller, rotor lag,
+RK4 (Sec. III-A) and the 64x64 depth / triangle id / colour render of every
+agent at its new pose (Sec. III-B), on synthetic inputs resident in HBM.  The
+library picks the launch form (one fused kernel for small batches, else the
+dynamics kernel, the spatial-order kernel and the render kernel).
 
 Default workload ("forest-256"): 256 agents in a seeded procedural forest of
 2,000 open 32-segment cylinders on a 40 x 40 m ground quad (128,002 triangles),
 64x64 depth + tri id + RGB, dt = 0.02 s, 200 seeded CTBR action steps (cycled).
 
-Printed: one JSON line with frames/s, ms/step, the roofline of the fused kernel
+Printed: one JSON line with frames/s, ms/step, the roofline of the render kernel
 (ALU-bound: VALU lane-operations of the ray-box and ray-triangle tests it
 performs, counted by a replay with the counting kernel variant, over its
 HIP-event time), HBM traffic if supplied from rocprofv3 counters, the serving
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-spatial-order", action="store_true",
+                    help="render agents in the given order instead of (scene, position) order")
     return ap.parse_args()
 
 
@@ -240,6 +244,7 @@ def main():
     s0 = agents.forest_starts(4, n, sc, params)
     acts_np = agents.random_actions(5, 200, n, params)
     ctx = sim.Context(0)
+    ctx.set_spatial_order(not args.no_spatial_order)
     sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
     info = ctx.scene_info(sid)
     views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))

@@ -60,16 +60,25 @@ typedef enum vf_status {
 } vf_status;
 
 enum { VF_RK4 = 0, VF_EULER = 1 };
-enum { VF_CTBR = 0, VF_SRT = 1 };
+enum { VF_CTBR = 0, VF_SRT = 1, VF_PS = 2, VF_LV = 3 };
 
 typedef struct vf_ctx vf_ctx; /* opaque; owned by the library */
 
-/* Airframe, controller and integrator parameters (Sec. III-A). 88 bytes. */
+/* Airframe, controller and integrator parameters (Sec. III-A). 128 bytes.
+ * Controllers (controller paragraph of Sec. III-A):
+ *   VF_CTBR  action (c m/s^2, Omega_des rad/s): tau = J k_rate (Omega_des - Omega) + Omega x J Omega, F = m c
+ *   VF_SRT   action = four rotor thrusts (N)
+ *   VF_PS    action (x_d, y_d, z_d m, yaw_d rad): a = -k_pos (p - p_d) - k_vel v
+ *   VF_LV    action (vx_d, vy_d, vz_d m/s, yaw_d rad): a = -k_vel (v - v_d)
+ * PS and LV are geometric (SE(3)) outer loops cascaded onto the CTBR rate loop: F = a + g e_z with its
+ * vertical part at least g/4 and its tilt at most max_tilt; R_d from F/|F| and the yaw heading;
+ * c = F . R e_z; Omega_des = -k_att e_R with e_R = 1/2 (R_d^T R - R^T R_d)^vee.
+ * Every controller's rotor thrusts are clamped to [0, f_max]. */
 typedef struct vf_dyn_params {
     float dt;            /* control step (s) */
     int32_t n_sub;       /* sub-steps per control step, >= 1; the controller runs every sub-step */
     int32_t integrator;  /* VF_RK4 or VF_EULER */
-    int32_t ctrl;        /* VF_CTBR or VF_SRT */
+    int32_t ctrl;        /* VF_CTBR, VF_SRT, VF_PS or VF_LV */
     float mass;          /* kg */
     float arm;           /* rotor distance from the centre (m); X frame at +-45 deg */
     float J[3];          /* diagonal inertia (kg m^2) */
@@ -79,19 +88,31 @@ typedef struct vf_dyn_params {
     float k_lin[3];      /* linear body-frame drag (N s/m) of Eq. (2) */
     float c_quad[3];     /* quadratic body-frame drag (N s^2/m^2) of Eq. (2) */
     float g;             /* gravity (m/s^2), along -z */
-    float k_rate[3];     /* CTBR body-rate gains (1/s) */
+    float k_rate[3];     /* body-rate gains (1/s) of the rate loop */
+    float k_pos[3];      /* PS position gains (1/s^2) */
+    float k_vel[3];      /* PS / LV velocity gains (1/s) */
+    float k_att[3];      /* PS / LV attitude gains (1/s) */
+    float max_tilt;      /* PS / LV tilt limit of the commanded thrust (rad), in (0, pi/2) */
 } vf_dyn_params;
 
-/* Per-agent camera/output descriptor. 40 bytes, 8-byte aligned. */
+/* Per-view camera/output descriptor. 72 bytes, 8-byte aligned.
+ * The camera frame has its optical axis along +x, image right along -y and image up along +z (the
+ * body frame's convention); mount_q rotates it into the body frame and mount_t places its centre, so a
+ * ray leaves p + R(q) mount_t along R(q) R(mount_q) (1, -u, v).  A quaternion with x = y = z = 0 (the
+ * all-zero default included) means no rotation.  Several views of one agent (a camera rig) are views
+ * whose env_idx entries name the same state slot (vf_render). */
 typedef struct vf_view {
     int32_t scene_id;    /* scene the agent flies in */
     int32_t H, W;        /* image size, 1..1024 each */
-    int32_t flags;       /* reserved, must be 0 */
+    int32_t flags;       /* the agent's sensor-noise key (vf_sensor_noise); ignored by the renderer */
     float hfov;          /* horizontal field of view (rad), (0, pi) */
     float near_clip;     /* hits closer than this are ignored (m) */
     float far_clip;      /* hits farther than this are ignored (m) */
     float miss_depth;    /* depth written where nothing is hit */
-    int64_t out_offset;  /* first output pixel of this agent */
+    int64_t out_offset;  /* first output pixel of this view */
+    float mount_q[4];    /* camera orientation in the body frame (w, x, y, z) */
+    float mount_t[3];    /* camera position in the body frame (m) */
+    int32_t swarm;       /* 0: none; k > 0: the agent flies in swarm k - 1 (vf_set_swarms) and sees its members */
 } vf_view;
 
 /* Summary of a built scene. */
@@ -188,7 +209,8 @@ vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float*
  * grad_state_in = (ds_{k+1}/ds_k)^T grad_state_out [n][17] and grad_action =
  * (ds_{k+1}/da_k)^T grad_state_out [n][4] (both overwritten).  The forward
  * sub-steps are recomputed from state_in.  Clamped rotor commands pass no
- * gradient; the square root of a zero rotor command passes none either. */
+ * gradient; the square root of a zero rotor command passes none either.
+ * Covers ctrl VF_CTBR and VF_SRT; VF_PS / VF_LV return VF_EINVAL. */
 vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const float* state_in,
                            const float* action, const float* grad_state_out, float* grad_state_in,
                            float* grad_action, void* stream);
@@ -214,6 +236,76 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
  * triangle give dist = +inf, tri_id = -1.  Equal distances go to the lower index. */
 vf_status vf_closest_point(vf_ctx* ctx, int64_t n, const float* points, const int32_t* scene_ids, int32_t scene_id0,
                            float max_dist, float* dist, float* closest, int32_t* tri_id, void* stream);
+
+/* Collision check of agents (the same distance module, used to end an episode on
+ * contact): for agent i at state slot env_idx[i] (identity if NULL) of state
+ * [n_slots][17] float32 [dev], in scene views[i].scene_id: dist [n] float32 [dev,
+ * out] to the nearest triangle (+inf beyond max_dist), rel [n][3] float32 [dev,
+ * out, nullable] = nearest point - position (0 when none within max_dist), and
+ * collided [n] uint8 [dev, out, nullable] = dist <= radius.  Bad slots or scenes
+ * give +inf / 0 and raise VF_EDEVICE at the next vf_sync_check. */
+vf_status vf_collision(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float* state, int64_t n_slots,
+                       const vf_view* views, float radius, float max_dist, float* dist, float* rel,
+                       uint8_t* collided, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Sensor extensions (Table I sensors; Sec. III-D Table II noise models).
+ * Noise draws come from Philox4x32-10 keyed by (seed, views[i].flags, pixel,
+ * stream): deterministic and independent of batch composition.
+ * ------------------------------------------------------------------------- */
+enum { VF_NOISE_NONE = 0, VF_NOISE_NORMAL = 1, VF_NOISE_SPECKLE = 2, VF_NOISE_SALT_PEPPER = 3 };
+
+typedef struct vf_noise {
+    int32_t depth_model;  /* depth: NORMAL D + s n, SPECKLE D (1 + s n), SALT_PEPPER p/2 -> far, p/2 -> near */
+    float depth_sigma;
+    float depth_p;
+    int32_t rgb_model;    /* colour: NORMAL / SPECKLE per channel (rounded, clamped); SALT_PEPPER whole pixel */
+    float rgb_sigma;      /* in 0..255 units for NORMAL */
+    float rgb_p;
+    uint64_t seed;
+} vf_noise;
+
+/* Apply noise in place to rendered depth [dev, nullable] and planar rgb [dev, nullable] of n
+ * agents laid out by views [n] [dev].  tri_id [dev, nullable]: misses (id -1) keep their depth;
+ * without ids every pixel is perturbed. */
+vf_status vf_sensor_noise(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
+                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb,
+                          int64_t out_pixels, void* stream);
+
+/* Per-triangle semantic labels of a scene ([T] int32 [dev], copied; NULL removes them). */
+vf_status vf_scene_set_labels(vf_ctx* ctx, int32_t scene_id, const int32_t* labels);
+
+/* Segmentation view: seg[p] = label of the hit triangle tri_id[p] (the triangle index itself if the
+ * scene has no labels), -1 on a miss, -2 - j on swarm member j; same layout as depth. */
+vf_status vf_segmentation(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
+                          const int32_t* tri_id, int32_t* seg, int64_t out_pixels, void* stream);
+
+/* IMU at the given states: out [n][6] = specific force (F_b + d) / m in the body frame (m/s^2) and
+ * body rates (rad/s), plus Normal noise of the given sigmas keyed by keys[i] (int32 [dev], NULL =
+ * agent index) and seed. */
+vf_status vf_imu(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int32_t* env_idx, const float* state,
+                 int64_t n_slots, float sigma_acc, float sigma_gyro, uint64_t seed, const int32_t* keys, float* out,
+                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Swarm mode (the swarm example of Sec. IV: agents see and avoid each other).
+ * Swarm s has the state slots slots[offsets[s] .. offsets[s + 1]) (host arrays, copied; the slots index
+ * the state array of the later calls).  A view with swarm = s + 1 renders the other members of swarm s
+ * as boxes of half sizes half_extent centred on their positions and turned with their attitude, in the
+ * flat colour rgb: member j (its position in the list) has id n_tris + j of the view's scene, and a
+ * member at the same depth as a triangle leaves the triangle.  Members are read at the state the render
+ * sees, so vf_step launches split (dynamics first) while swarms are set.  vf_collision reports for swarm
+ * views the smaller of the mesh distance and the distance to the nearest other member's bounding sphere
+ * (radius |half_extent|).  Member pixels pass no gradient in vf_render_backward.  n_swarms = 0 clears.
+ * ------------------------------------------------------------------------- */
+vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, const int32_t* slots,
+                        const float half_extent[3], const uint8_t rgb[3]);
+
+/* Render order of split launches (vf_step split form, vf_render, the server): with enable != 0 (the
+ * default) a batch of 64 .. 4096 agents is first sorted by (scene id, 2-D Morton code of position) in
+ * one small kernel, so that the agents one XCD renders share a scene region and its L2 holds the part
+ * of the BVH they touch.  The order changes which workgroup renders an agent, never the results. */
+vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
 
 /* How vf_step with views launches its work.  VF_LAUNCH_SPLIT: a dynamics
  * kernel (one thread per agent) then the render kernel, two launches on the

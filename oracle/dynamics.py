@@ -20,6 +20,15 @@ Readings of the passages the paper leaves open:
     SRT: the action is the four rotor thrusts, clamped the same way.
   * Eq. (1): q_dot = 1/2 q (x) (0, Omega) with the Hamilton product, R from the
     normalised q; gravity (0, 0, -g).  After every sub-step q is normalised.
+  * PS and LV (same paragraph; geometric control after Lee, Leok and McClamroch,
+    CDC 2010, cascaded onto the CTBR rate loop):
+        PS action (x_d, y_d, z_d, psi_d):  a = -K_p (p - p_d) - K_v v
+        LV action (vx_d, vy_d, vz_d, psi_d): a = -K_v (v - v_d)
+        F = a + g e_z, its vertical part raised to at least g/4 and its
+        horizontal part shortened so the tilt of F stays within max_tilt;
+        b3 = F/|F|, b2 = b3 x (cos psi_d, sin psi_d, 0) normalised, b1 = b2 x b3,
+        R_d = [b1 b2 b3];  c = F . R e_z;  e_R = 1/2 (R_d^T R - R^T R_d)^vee;
+        Omega_des = -K_R e_R, then the CTBR law with (c, Omega_des).
 """
 import numpy as np
 
@@ -27,6 +36,9 @@ RK4 = 0
 EULER = 1
 CTBR = 0
 SRT = 1
+PS = 2
+LV = 3
+MIN_LIFT = 0.25     # vertical part of the commanded acceleration at least MIN_LIFT * g
 
 
 def quat_mul(a, b):
@@ -89,16 +101,55 @@ def allocation_matrix(params):
     return a
 
 
+def vee(m):
+    """The vector of a skew-symmetric matrix: vee([w]_x) = w.  [...,3,3] -> [...,3]"""
+    return np.stack([m[..., 2, 1], m[..., 0, 2], m[..., 1, 0]], axis=-1)
+
+
+def outer_loop(state, action, params):
+    """PS / LV: collective acceleration c [N] and body-rate command Omega_des [N,3] for the rate loop."""
+    p, q, v = state[:, 0:3], state[:, 3:7], state[:, 7:10]
+    rot = quat_to_rot(q / np.linalg.norm(q, axis=1, keepdims=True))
+    kp = np.asarray(params["k_pos"], dtype=np.float64)
+    kv = np.asarray(params["k_vel"], dtype=np.float64)
+    ka = np.asarray(params["k_att"], dtype=np.float64)
+    g = params["g"]
+    if params["ctrl"] == PS:
+        acc = -kp * (p - action[:, 0:3]) - kv * v
+    else:
+        acc = -kv * (v - action[:, 0:3])
+    f = acc + np.array([0.0, 0.0, g])
+    f[:, 2] = np.maximum(f[:, 2], MIN_LIFT * g)
+    horiz = np.hypot(f[:, 0], f[:, 1])
+    limit = f[:, 2] * np.tan(params["max_tilt"])
+    scale = np.where(horiz > limit, limit / np.where(horiz > 0, horiz, 1.0), 1.0)
+    f[:, 0:2] *= scale[:, None]
+    b3 = f / np.linalg.norm(f, axis=1, keepdims=True)
+    psi = action[:, 3]
+    heading = np.stack([np.cos(psi), np.sin(psi), np.zeros_like(psi)], axis=1)
+    b2 = np.cross(b3, heading)
+    b2 /= np.linalg.norm(b2, axis=1, keepdims=True)
+    b1 = np.cross(b2, b3)
+    rd = np.stack([b1, b2, b3], axis=2)                      # columns b1, b2, b3
+    c = np.einsum("ni,ni->n", f, rot[:, :, 2])
+    rdt_r = np.einsum("nji,njk->nik", rd, rot)
+    e_r = 0.5 * vee(rdt_r - np.swapaxes(rdt_r, 1, 2))
+    return c, -ka * e_r
+
+
 def controller(state, action, params):
-    """Desired rotor thrusts f_des [N,4] from CTBR or SRT commands (held over a sub-step)."""
+    """Desired rotor thrusts f_des [N,4] from CTBR, SRT, PS or LV commands (held over a sub-step)."""
     f_max = params["f_max"]
     if params["ctrl"] == SRT:
         return np.clip(action.astype(np.float64), 0.0, f_max)
     jd = np.asarray(params["J"], dtype=np.float64)
     kr = np.asarray(params["k_rate"], dtype=np.float64)
     om = state[:, 10:13]
-    c = action[:, 0]
-    om_des = action[:, 1:4]
+    if params["ctrl"] in (PS, LV):
+        c, om_des = outer_loop(state, action, params)
+    else:
+        c = action[:, 0]
+        om_des = action[:, 1:4]
     force = params["mass"] * c
     torque = jd * kr * (om_des - om) + np.cross(om, jd * om)
     rhs = np.concatenate([force[:, None], torque], axis=1)

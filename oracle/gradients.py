@@ -98,8 +98,10 @@ def depth_pose_gradient(state_row, scene, view, pixels, h=1e-6):
         e = np.zeros(17)
         e[j] = h
         dp = render.render_view(s + e, scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
-                                view.get("miss_depth"), with_mask=False, pixels=pixels)["depth"]
+                                view.get("miss_depth"), with_mask=False, pixels=pixels,
+                                mount=view.get("mount"))["depth"]
         dm = render.render_view(s - e, scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
-                                view.get("miss_depth"), with_mask=False, pixels=pixels)["depth"]
+                                view.get("miss_depth"), with_mask=False, pixels=pixels,
+                                mount=view.get("mount"))["depth"]
         g[:, j] = (dp - dm) / (2 * h)
     return g

@@ -85,6 +85,51 @@ def cast(orig, dirs, verts, tris, near=0.01, far=100.0, with_mask=True):
     return out
 
 
+def cast_boxes(orig, dirs, centers, quats, half, near=0.01, far=100.0):
+    """Entry of each ray [R] into the nearest of K oriented boxes (the body boxes of other agents),
+    by the slab method in each box's frame, FP64.
+
+    A box is hit where the ray enters it at t in [near, far]; a ray starting inside a box does not
+    see that box.  Equal entries go to the lower box index.  Returns t [R] (inf on a miss), k [R]
+    (-1 on a miss) and two mask quantities: edge, the distance of the entry point to the border of
+    the face it enters through, and gap, for a ray missing a box, (t_enter - t_exit) |d| minimised
+    over the boxes (how far the slab intervals miss).
+    """
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    r = dirs.shape[0]
+    orig = np.broadcast_to(np.asarray(orig, dtype=np.float64).reshape(-1, 3), (r, 3))
+    half = np.asarray(half, dtype=np.float64)
+    t_best = np.full(r, np.inf)
+    k_best = np.full(r, -1, dtype=np.int64)
+    edge = np.full(r, np.inf)
+    gap = np.full(r, np.inf)
+    for k in range(np.asarray(centers).shape[0]):
+        rot = quat_to_rot(np.asarray(quats[k], dtype=np.float64))
+        o = (orig - np.asarray(centers[k], dtype=np.float64)) @ rot      # R^T (o - c), row-wise
+        d = dirs @ rot
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1 = (-half - o) / d
+            t2 = (half - o) / d
+        lo = np.where(d == 0, np.where(np.abs(o) <= half, -np.inf, np.inf), np.minimum(t1, t2))
+        hi = np.where(d == 0, np.where(np.abs(o) <= half, np.inf, -np.inf), np.maximum(t1, t2))
+        t_in = lo.max(axis=1)
+        t_out = hi.min(axis=1)
+        hit = (t_in <= t_out) & (t_in >= near) & (t_in <= far)
+        take = hit & (t_in < t_best)
+        if take.any():
+            axis = lo.argmax(axis=1)
+            x = o + t_in[:, None] * d
+            margin = half[None, :] - np.abs(x)
+            margin[np.arange(r), axis] = np.inf
+            edge = np.where(take, margin.min(axis=1), edge)
+            t_best = np.where(take, t_in, t_best)
+            k_best = np.where(take, k, k_best)
+        miss = ~(t_in <= t_out) & np.isfinite(t_in) & np.isfinite(t_out)
+        g = np.where(miss, (t_in - t_out) * np.linalg.norm(dirs, axis=1), np.inf)
+        gap = np.minimum(gap, g)
+    return {"t": t_best, "k": k_best, "edge": edge, "gap": gap}
+
+
 def closest_points(points, verts, tris):
     """Nearest point on the mesh to each query point (exact point-triangle distance, brute force)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
@@ -123,6 +168,28 @@ def camera_dirs_body(h, w, hfov):
     d[..., 1] = -u[None, :]
     d[..., 2] = v[:, None]
     return d
+
+
+def camera_pose(state_row, mount=None):
+    """The camera's own pose row for a camera mounted at (q_m, t_m) in the body frame: position
+    p + R(q) t_m and orientation q (x) q_m, so that its rays are R(q) R(q_m) (1, -u, v).  A mount
+    quaternion with zero vector part is no rotation."""
+    s = np.array(state_row, dtype=np.float64)
+    if mount is None:
+        return s
+    qm = np.asarray(mount[0], dtype=np.float64)
+    tm = np.asarray(mount[1], dtype=np.float64)
+    rot = quat_to_rot(s[3:7])
+    out = s.copy()
+    out[0:3] = s[0:3] + rot @ tm
+    if np.any(qm[1:4] != 0):
+        qb = s[3:7] / np.linalg.norm(s[3:7])
+        qm = qm / np.linalg.norm(qm)
+        w1, x1, y1, z1 = qb
+        w2, x2, y2, z2 = qm
+        out[3:7] = [w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                    w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2]
+    return out
 
 
 def camera_rays(state_row, h, w, hfov):
@@ -172,13 +239,18 @@ def mask_from(out, eps_edge=1e-5, eps_tie=1e-5):
 
 
 def render_view(state_row, scene, h=64, w=64, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None,
-                eps_edge=1e-5, eps_tie=1e-5, with_mask=True, pixels=None, cull=True):
+                eps_edge=1e-5, eps_tie=1e-5, with_mask=True, pixels=None, cull=True, mount=None, others=None):
     """Depth [H,W] (or [P] for a pixel subset), triangle id, planar RGB and the comparison mask.
 
     pixels: optional int array of flat pixel indices (row * W + col) to render only those.
     cull: pre-filter the triangles with frustum_keep() (exact: never changes a result).
+    mount: optional camera mount (q_m (w,x,y,z), t_m) in the body frame, see camera_pose().
+    others: optional swarm members seen by this camera, a dict with centers [K,3], quats [K,4],
+      half [3] (body-box half sizes), rgb [3] and ids [K] (the id each member's pixels get; above
+      every triangle index).  A member nearer than the mesh hides it; equal depths keep the mesh.
     """
     miss_depth = far if miss_depth is None else miss_depth
+    state_row = camera_pose(state_row, mount)
     o, d = camera_rays(state_row, h, w, hfov)
     d = d.reshape(-1, 3)
     if pixels is not None:
@@ -190,13 +262,29 @@ def render_view(state_row, scene, h=64, w=64, hfov=np.pi / 2, near=0.01, far=100
     if keep.size:
         out["id"] = np.where(out["id"] >= 0, keep[np.maximum(out["id"], 0)], -1)
     hit = out["id"] >= 0
-    depth = np.where(hit, out["t"], miss_depth)
     rgb = np.zeros((3, d.shape[0]), dtype=np.uint8)
     if "rgb" in scene and scene["rgb"] is not None:
         rgb[:, hit] = np.asarray(scene["rgb"])[out["id"][hit]].T
+    swarm_mask = np.zeros(d.shape[0], dtype=bool)
+    if others is not None and len(others["centers"]):
+        b = cast_boxes(o, d, others["centers"], others["quats"], others["half"], near, far)
+        mesh_t = np.where(hit, out["t"], np.inf)
+        take = (b["k"] >= 0) & (b["t"] < mesh_t)
+        out["t"] = np.where(take, b["t"], out["t"])
+        out["id"] = np.where(take, np.asarray(others["ids"])[np.maximum(b["k"], 0)], out["id"])
+        rgb[:, take] = np.asarray(others["rgb"], dtype=np.uint8)[:, None]
+        hit = hit | take
+        scale = np.maximum(1.0, np.where(np.isfinite(b["t"]), b["t"], 1.0))
+        both = np.isfinite(b["t"]) & np.isfinite(mesh_t)
+        close = np.zeros_like(both)
+        close[both] = np.abs(b["t"][both] - mesh_t[both]) < eps_tie * np.maximum(mesh_t[both], 1e-300)
+        swarm_mask = ((np.isfinite(b["t"]) & (b["edge"] < eps_edge * scale)) | (b["gap"] < eps_edge * scale) | close
+                      | (np.isfinite(b["t"]) & ((np.abs(b["t"] - near) < 1e-6 * scale) |
+                                                (np.abs(b["t"] - far) < 1e-6 * scale))))
+    depth = np.where(hit, out["t"], miss_depth)
     res = {"depth": depth, "id": out["id"].astype(np.int64), "rgb": rgb, "threads": out["threads"]}
     if with_mask:
-        res["mask"] = mask_from(out, eps_edge, eps_tie)
+        res["mask"] = mask_from(out, eps_edge, eps_tie) | swarm_mask
         res["raw"] = out
     if pixels is None:
         res["depth"] = res["depth"].reshape(h, w)

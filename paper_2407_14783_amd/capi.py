@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(_HERE, "libvisfly_hip.so")
 
 VF_OK, VF_EINVAL, VF_ENOMEM, VF_ENOSCENE, VF_EHIP, VF_EBUSY, VF_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 VF_RK4, VF_EULER = 0, 1
-VF_CTBR, VF_SRT = 0, 1
+VF_CTBR, VF_SRT, VF_PS, VF_LV = 0, 1, 2, 3
 VF_LAUNCH_SPLIT, VF_LAUNCH_FUSED, VF_LAUNCH_AUTO = 0, 1, 2
+VF_NOISE_NONE, VF_NOISE_NORMAL, VF_NOISE_SPECKLE, VF_NOISE_SALT_PEPPER = 0, 1, 2, 3
 STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE", -4: "VF_EHIP", -5: "VF_EBUSY",
                 -6: "VF_EDEVICE"}
 
@@ -24,7 +25,7 @@ EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_sc
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
             "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_server_create",
             "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
-            "vf_closest_point")
+            "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order")
 
 
 class DynParams(ctypes.Structure):
@@ -32,7 +33,14 @@ class DynParams(ctypes.Structure):
                 ("ctrl", ctypes.c_int32), ("mass", ctypes.c_float), ("arm", ctypes.c_float),
                 ("J", ctypes.c_float * 3), ("tau_motor", ctypes.c_float), ("kappa_yaw", ctypes.c_float),
                 ("f_max", ctypes.c_float), ("k_lin", ctypes.c_float * 3), ("c_quad", ctypes.c_float * 3),
-                ("g", ctypes.c_float), ("k_rate", ctypes.c_float * 3)]
+                ("g", ctypes.c_float), ("k_rate", ctypes.c_float * 3), ("k_pos", ctypes.c_float * 3),
+                ("k_vel", ctypes.c_float * 3), ("k_att", ctypes.c_float * 3), ("max_tilt", ctypes.c_float)]
+
+
+class Noise(ctypes.Structure):
+    _fields_ = [("depth_model", ctypes.c_int32), ("depth_sigma", ctypes.c_float), ("depth_p", ctypes.c_float),
+                ("rgb_model", ctypes.c_int32), ("rgb_sigma", ctypes.c_float), ("rgb_p", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
 
 
 class SceneInfo(ctypes.Structure):
@@ -43,14 +51,15 @@ class SceneInfo(ctypes.Structure):
 
 
 VIEW_DTYPE = np.dtype([("scene_id", "<i4"), ("H", "<i4"), ("W", "<i4"), ("flags", "<i4"), ("hfov", "<f4"),
-                       ("near_clip", "<f4"), ("far_clip", "<f4"), ("miss_depth", "<f4"), ("out_offset", "<i8")])
+                       ("near_clip", "<f4"), ("far_clip", "<f4"), ("miss_depth", "<f4"), ("out_offset", "<i8"),
+                       ("mount_q", "<f4", 4), ("mount_t", "<f4", 3), ("swarm", "<i4")])
 NODE_DTYPE = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
                        ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<i4", 4), ("count", "u1", 4),
                        ("order_lo", "<u4"), ("order_hi", "<u4"), ("pad", "<u4")])
 TRI_DTYPE = np.dtype([("v0", "<f4", 3), ("id", "<i4"), ("e1", "<f4", 3), ("pad1", "<f4"), ("e2", "<f4", 3),
                       ("pad2", "<f4")])
-assert VIEW_DTYPE.itemsize == 40 and NODE_DTYPE.itemsize == 128 and TRI_DTYPE.itemsize == 48
-assert ctypes.sizeof(DynParams) == 88
+assert VIEW_DTYPE.itemsize == 72 and NODE_DTYPE.itemsize == 128 and TRI_DTYPE.itemsize == 48
+assert ctypes.sizeof(DynParams) == 128 and ctypes.sizeof(Noise) == 32
 
 
 class VfError(RuntimeError):
@@ -77,7 +86,14 @@ def _load():
         "vf_render_backward": ([P, I64, P, P, I32, I32, P, P, I64, P, P], I32),
         "vf_set_stats": ([P, I32], I32),
         "vf_set_launch_mode": ([P, I32], I32),
+        "vf_set_spatial_order": ([P, I32], I32),
         "vf_closest_point": ([P, I64, P, P, I32, ctypes.c_float, P, P, P, P], I32),
+        "vf_sensor_noise": ([P, I64, P, I32, I32, ctypes.POINTER(Noise), P, P, P, I64, P], I32),
+        "vf_scene_set_labels": ([P, I32, P], I32),
+        "vf_set_swarms": ([P, I32, P, P, P, P], I32),
+        "vf_collision": ([P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P, P, P], I32),
+        "vf_segmentation": ([P, I64, P, I32, I32, P, P, I64, P], I32),
+        "vf_imu": ([P, ctypes.POINTER(DynParams), I64, P, P, I64, ctypes.c_float, ctypes.c_float, U64, P, P, P], I32),
         "vf_stats_read": ([P, ctypes.POINTER(U64), I32], I32),
         "vf_sync_check": ([P, P], I32),
         "vf_mem_usage": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
@@ -120,4 +136,8 @@ def params_struct(p):
     s.c_quad[:] = list(p["c_quad"])
     s.g = p["g"]
     s.k_rate[:] = list(p["k_rate"])
+    s.k_pos[:] = list(p["k_pos"])
+    s.k_vel[:] = list(p["k_vel"])
+    s.k_att[:] = list(p["k_att"])
+    s.max_tilt = p["max_tilt"]
     return s

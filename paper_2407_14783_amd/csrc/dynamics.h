@@ -1,6 +1,6 @@
 // Device-side quadrotor dynamics (Sec. III-A): Eq. (1) rigid body, Eq. (2) drag,
 // Eq. (3) thrust and moment with a rotor reaction yaw torque, Eq. (4) first-order
-// rotor lag, the CTBR and SRT controllers, RK4 or explicit Euler with sub-steps.
+// rotor lag, the CTBR, SRT, PS and LV controllers, RK4 or explicit Euler with sub-steps.
 //
 // Readings of what the paper leaves open (all shared with the oracle's docstring
 // by statement, not by code): X frame with rotors at a (1,-1), a (-1,1), a (1,1),
@@ -38,6 +38,23 @@ __device__ __forceinline__ void quat_rot(const float q[4], float r[9]) {
     r[6] = 2.0f * (xz - wy);        r[7] = 2.0f * (yz + wx);        r[8] = 1.0f - 2.0f * (xx + yy);
 }
 
+// Camera pose of a view: origin p + R mount_t and rotation R R(mount_q) (row major).
+// A mount quaternion with zero vector part is no rotation.
+__device__ __forceinline__ void camera_pose(const float pose[17], const vf_view& vw, float o[3], float rc[9]) {
+    float r[9];
+    quat_rot(pose + 3, r);
+    for (int i = 0; i < 3; ++i)
+        o[i] = pose[i] + (r[3 * i] * vw.mount_t[0] + r[3 * i + 1] * vw.mount_t[1] + r[3 * i + 2] * vw.mount_t[2]);
+    if (vw.mount_q[1] == 0.0f && vw.mount_q[2] == 0.0f && vw.mount_q[3] == 0.0f) {
+        for (int i = 0; i < 9; ++i) rc[i] = r[i];
+        return;
+    }
+    float m[9];
+    quat_rot(vw.mount_q, m);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) rc[3 * i + j] = r[3 * i] * m[j] + r[3 * i + 1] * m[3 + j] + r[3 * i + 2] * m[6 + j];
+}
+
 // Eq. (1) right-hand side at rotor speeds w.
 __device__ __forceinline__ void derivative(const DynConst& c, const Vec13& y, const float w[4], Vec13& d) {
     float f[4] = {w[0] * w[0], w[1] * w[1], w[2] * w[2], w[3] * w[3]};
@@ -73,17 +90,61 @@ __device__ __forceinline__ void derivative(const DynConst& c, const Vec13& y, co
     d.w[2] = (tau[2] - cz) * c.inv_J[2];
 }
 
+// PS / LV outer loop (geometric control on SE(3), cascaded onto the rate loop):
+// commanded acceleration -> thrust direction b3 (lift at least g/4, tilt at most
+// max_tilt) -> R_d = [b1 b2 b3] with b2 = b3 x heading(yaw_d) normalised ->
+// collective c = F . R e_z and rate command Omega_des = -k_att e_R,
+// e_R = 1/2 (R_d^T R - R^T R_d)^vee.
+__device__ __forceinline__ void outer_loop(const DynConst& c, const float s[17], const float a[4], float& cc,
+                                           float om_des[3]) {
+    float f[3];
+    if (c.ctrl == VF_PS) {
+        for (int i = 0; i < 3; ++i) f[i] = -c.k_pos[i] * (s[i] - a[i]) - c.k_vel[i] * s[7 + i];
+    } else {
+        for (int i = 0; i < 3; ++i) f[i] = -c.k_vel[i] * (s[7 + i] - a[i]);
+    }
+    f[2] = fmaxf(f[2] + c.g, c.min_lift);
+    float hz = sqrtf(f[0] * f[0] + f[1] * f[1]);
+    float lim = f[2] * c.tan_tilt;
+    if (hz > lim) {
+        float sc = lim / hz;
+        f[0] *= sc;
+        f[1] *= sc;
+    }
+    float inv = 1.0f / sqrtf(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    float b3[3] = {f[0] * inv, f[1] * inv, f[2] * inv};
+    float sp, cp;
+    sincosf(a[3], &sp, &cp);
+    // b3 x (cos, sin, 0); its norm is at least b3_z > 0
+    float b2[3] = {-b3[2] * sp, b3[2] * cp, b3[0] * sp - b3[1] * cp};
+    float in2 = 1.0f / sqrtf(b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2]);
+    for (int i = 0; i < 3; ++i) b2[i] *= in2;
+    float b1[3] = {b2[1] * b3[2] - b2[2] * b3[1], b2[2] * b3[0] - b2[0] * b3[2], b2[0] * b3[1] - b2[1] * b3[0]};
+    float r[9];
+    quat_rot(s + 3, r);
+    cc = f[0] * r[2] + f[1] * r[5] + f[2] * r[8];
+    // M = R_d^T R: M_ij = b_i . (column j of R)
+    auto dotc = [&](const float b[3], int j) { return b[0] * r[j] + b[1] * r[3 + j] + b[2] * r[6 + j]; };
+    float m21 = dotc(b3, 1), m12 = dotc(b2, 2), m02 = dotc(b1, 2), m20 = dotc(b3, 0), m10 = dotc(b2, 0),
+          m01 = dotc(b1, 1);
+    om_des[0] = -c.k_att[0] * 0.5f * (m21 - m12);
+    om_des[1] = -c.k_att[1] * 0.5f * (m02 - m20);
+    om_des[2] = -c.k_att[2] * 0.5f * (m10 - m01);
+}
+
 // Desired rotor thrusts (clamped) from the action at the sub-step start.
 __device__ __forceinline__ void controller(const DynConst& c, const float s[17], const float a[4], float f[4]) {
     if (c.ctrl == VF_SRT) {
         for (int i = 0; i < 4; ++i) f[i] = a[i];
     } else {
+        float cmd[4] = {a[0], a[1], a[2], a[3]};
+        if (c.ctrl == VF_PS || c.ctrl == VF_LV) outer_loop(c, s, a, cmd[0], cmd + 1);
         const float* om = s + 10;
         float jo[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
-        float t0 = c.kJ[0] * (a[1] - om[0]) + (om[1] * jo[2] - om[2] * jo[1]);
-        float t1 = c.kJ[1] * (a[2] - om[1]) + (om[2] * jo[0] - om[0] * jo[2]);
-        float t2 = c.kJ[2] * (a[3] - om[2]) + (om[0] * jo[1] - om[1] * jo[0]);
-        float u0 = c.mass * a[0], u1 = t0 * c.inv_a, u2 = t1 * c.inv_a, u3 = t2 * c.inv_kappa;
+        float t0 = c.kJ[0] * (cmd[1] - om[0]) + (om[1] * jo[2] - om[2] * jo[1]);
+        float t1 = c.kJ[1] * (cmd[2] - om[1]) + (om[2] * jo[0] - om[0] * jo[2]);
+        float t2 = c.kJ[2] * (cmd[3] - om[2]) + (om[0] * jo[1] - om[1] * jo[0]);
+        float u0 = c.mass * cmd[0], u1 = t0 * c.inv_a, u2 = t1 * c.inv_a, u3 = t2 * c.inv_kappa;
         f[0] = 0.25f * ((u0 + u3) - (u1 + u2));
         f[1] = 0.25f * ((u0 + u3) + (u1 + u2));
         f[2] = 0.25f * ((u0 - u3) + (u1 - u2));

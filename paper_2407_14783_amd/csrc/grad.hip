@@ -11,7 +11,8 @@
 // and the CTBR mixer / rate controller.
 //
 // k_render_backward: depth t = n.(V0 - o) / n.d on the hit triangle's plane;
-// dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B.  Per agent the pixel
+// dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B with d_B = R_m d_cam and
+// o = p + R t_m for a camera mounted at (R_m, t_m).  Per agent the pixel
 // sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix) are reduced in
 // a fixed order, then chained through R and the quaternion normalisation.
 #include "dynamics.h"
@@ -310,7 +311,12 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     float q[4] = {st[3], st[4], st[5], st[6]};
     float rot[9];
     quat_rot(q, rot);
-    const float o[3] = {st[0], st[1], st[2]};
+    // camera mount: origin p + R t_m, body-frame direction R_m d_cam
+    float m[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    if (!(vw.mount_q[1] == 0.0f && vw.mount_q[2] == 0.0f && vw.mount_q[3] == 0.0f)) quat_rot(vw.mount_q, m);
+    const float tm[3] = {vw.mount_t[0], vw.mount_t[1], vw.mount_t[2]};
+    float o[3];
+    for (int i = 0; i < 3; ++i) o[i] = st[i] + (rot[3 * i] * tm[0] + rot[3 * i + 1] * tm[1] + rot[3 * i + 2] * tm[2]);
     const float tan_h = tanf(0.5f * vw.hfov);
     float acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.f;
@@ -322,16 +328,16 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
         float g = a.grad_depth[at];
         if (id < 0 || g == 0.0f) continue;
         if (id >= sc.n_tris) {
-            bad = kErrTriId;
+            if (vw.swarm <= 0) bad = kErrTriId;   // ids past the mesh name swarm members: no gradient
             continue;
         }
         const Tri tr = sc.tris[sc.sorted_of[id]];
         int r = pix / vw.W, cc = pix - r * vw.W;
         float u = (2.0f * ((float)cc + 0.5f) / (float)vw.W - 1.0f) * tan_h;
         float v = (1.0f - 2.0f * ((float)r + 0.5f) / (float)vw.H) * tan_h * ((float)vw.H / (float)vw.W);
-        float db[3] = {1.0f, -u, v};
-        float d[3] = {rot[0] + rot[1] * db[1] + rot[2] * db[2], rot[3] + rot[4] * db[1] + rot[5] * db[2],
-                      rot[6] + rot[7] * db[1] + rot[8] * db[2]};
+        float db[3] = {m[0] - m[1] * u + m[2] * v, m[3] - m[4] * u + m[5] * v, m[6] - m[7] * u + m[8] * v};
+        float d[3] = {rot[0] * db[0] + rot[1] * db[1] + rot[2] * db[2], rot[3] * db[0] + rot[4] * db[1] + rot[5] * db[2],
+                      rot[6] * db[0] + rot[7] * db[1] + rot[8] * db[2]};
         float n[3] = {tr.e1y * tr.e2z - tr.e1z * tr.e2y, tr.e1z * tr.e2x - tr.e1x * tr.e2z,
                       tr.e1x * tr.e2y - tr.e1y * tr.e2x};
         float nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
@@ -355,6 +361,9 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
         for (int k = 0; k < 3; ++k) gs[k] += red[k][0];
         float G[9];
         for (int k = 0; k < 9; ++k) G[k] = red[3 + k][0];
+        // the origin p + R t_m also moves with R
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * tm[j];
         float inv = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
         float qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
         float lqn[4], lq[4];

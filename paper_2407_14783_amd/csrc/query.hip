@@ -5,8 +5,11 @@
 // box first and a subtree is skipped when its box is farther than the best
 // distance found so far.  The closest point on a triangle is found by the
 // Voronoi-region method (Ericson, Real-Time Collision Detection, 5.1.5):
-// vertex, edge or face region from the signs of a few dot products.
-// Equal distances go to the lower caller triangle index.
+// vertex, edge or face region from the signs of a few dot products (a point in the face region is
+// projected onto the plane directly).
+// Equal distances go to the lower caller triangle index.  In agent mode the query
+// points are the agents' positions (state rows) and the flag dist <= radius is
+// the collision test that ends an episode.
 #include <float.h>
 
 #include "vf_internal.h"
@@ -65,23 +68,44 @@ __device__ __forceinline__ void closest_on_triangle(const float p[3], const floa
         for (int i = 0; i < 3; ++i) out[i] = a[i] + e1[i] + w * (e2[i] - e1[i]);
         return;
     }
-    float denom = 1.0f / (va + vb + vc);   // face interior
-    float v = vb * denom, w = vc * denom;
-    for (int i = 0; i < 3; ++i) out[i] = a[i] + v * e1[i] + w * e2[i];
+    // face interior: orthogonal projection onto the plane (no cancellation in barycentric weights)
+    float n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    float s = (ap[0] * n[0] + ap[1] * n[1] + ap[2] * n[2]) / (n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int i = 0; i < 3; ++i) out[i] = p[i] - s * n[i];
 }
 
 __global__ void __launch_bounds__(128) k_closest_point(QueryArgs q) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= q.n) return;
-    int32_t sid = q.scene_ids ? q.scene_ids[i] : q.scene_id0;
-    if (sid < 0 || sid >= q.n_scenes || !q.scenes[sid].valid) {
+    int32_t sid;
+    float p[3];
+    bool ok = true;
+    if (q.state) {
+        int64_t slot = q.env_idx ? (int64_t)q.env_idx[i] : (int64_t)i;
+        if (slot < 0 || slot >= q.n_slots) {
+            atomicOr(q.err, kErrSlot);
+            ok = false;
+            slot = 0;
+        }
+        for (int k = 0; k < 3; ++k) p[k] = q.state[slot * 17 + k];
+        sid = q.views[i].scene_id;
+    } else {
+        sid = q.scene_ids ? q.scene_ids[i] : q.scene_id0;
+        for (int k = 0; k < 3; ++k) p[k] = q.points[3 * (int64_t)i + k];
+    }
+    if (ok && (sid < 0 || sid >= q.n_scenes || !q.scenes[sid].valid)) {
         atomicOr(q.err, kErrScene);
+        ok = false;
+    }
+    if (!ok) {
         q.dist[i] = INFINITY;
         if (q.tri_id) q.tri_id[i] = -1;
+        if (q.collided) q.collided[i] = 0;
+        if (q.rel)
+            for (int k = 0; k < 3; ++k) q.rel[3 * (int64_t)i + k] = 0.0f;
         return;
     }
     const SceneDesc sc = q.scenes[sid];
-    const float p[3] = {q.points[3 * (int64_t)i], q.points[3 * (int64_t)i + 1], q.points[3 * (int64_t)i + 2]};
     float best = q.max_dist * q.max_dist;
     int32_t best_id = -1;
     float best_pt[3] = {0.f, 0.f, 0.f};
@@ -151,7 +175,40 @@ __global__ void __launch_bounds__(128) k_closest_point(QueryArgs q) {
         }
     }
     if (overflow) atomicOr(q.err, kErrStack);
-    q.dist[i] = best_id >= 0 ? sqrtf(best) : INFINITY;
+    float d = best_id >= 0 ? sqrtf(best) : INFINITY;
+    if (q.state && q.views[i].swarm > 0) {
+        // other members of the agent's swarm, as bounding spheres
+        const int sw = q.views[i].swarm;
+        if (sw > q.swarm.n) {
+            atomicOr(q.err, kErrView);
+        } else {
+            const int64_t self = q.env_idx ? (int64_t)q.env_idx[i] : (int64_t)i;
+            for (int j = q.swarm.off[sw - 1]; j < q.swarm.off[sw]; ++j) {
+                const int64_t ms = q.swarm.slots[j];
+                if (ms == self) continue;
+                if (ms < 0 || ms >= q.n_slots) {
+                    atomicOr(q.err, kErrSlot);
+                    continue;
+                }
+                const float* mp = q.state + ms * 17;
+                const float vx = mp[0] - p[0], vy = mp[1] - p[1], vz = mp[2] - p[2];
+                const float c = sqrtf(vx * vx + vy * vy + vz * vz);
+                const float dm = c - q.swarm.radius;
+                if (dm < d) {
+                    d = dm;
+                    best_id = -2;
+                    const float s = c > 0.0f ? dm / c : 0.0f;
+                    best_pt[0] = p[0] + s * vx;
+                    best_pt[1] = p[1] + s * vy;
+                    best_pt[2] = p[2] + s * vz;
+                }
+            }
+        }
+    }
+    q.dist[i] = d;
+    if (q.collided) q.collided[i] = d <= q.radius ? 1 : 0;
+    if (q.rel)
+        for (int k = 0; k < 3; ++k) q.rel[3 * (int64_t)i + k] = best_id != -1 ? best_pt[k] - p[k] : 0.0f;
     if (q.tri_id) q.tri_id[i] = best_id;
     if (q.closest) {
         q.closest[3 * (int64_t)i] = best_pt[0];

@@ -56,21 +56,29 @@ struct TraceStats {
     unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits;
 };
 
-template <bool STATS>
-__device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, const float o[3], const float d[3],
-                                             float t_near, float t_far, float& t_best, int32_t& id_best,
-                                             uint32_t* err, TraceStats& ts) {
+template <int NR, bool STATS>
+__device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&valid)[NR], const float o[3],
+                                             const float (&d)[NR][3], float t_near, float t_far,
+                                             float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
+                                             TraceStats& ts) {
     const Node4 CONST_AS* nodes = (const Node4 CONST_AS*)sc.nodes;
     const Tri CONST_AS* tris = (const Tri CONST_AS*)sc.tris;
-    const float inv[3] = {safe_inv(d[0]), safe_inv(d[1]), safe_inv(d[2])};
+    float inv[NR][3];
+    int n_valid = 0;
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        for (int k = 0; k < 3; ++k) inv[r][k] = safe_inv(d[r][k]);
+        t_best[r] = t_far;
+        id_best[r] = -1;
+        any = any || valid[r];
+        n_valid += valid[r] ? 1 : 0;
+    }
     // 1 + 2 gamma_3 (Ize 2013) keeps the slab test conservative in float32
     const float grow = 1.0000004f;
-    int oct = (d[0] < 0.f ? 1 : 0) | (d[1] < 0.f ? 2 : 0) | (d[2] < 0.f ? 4 : 0);
+    int oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
     oct = uniform_i(oct);
-    t_best = t_far;
-    id_best = -1;
-    const uint64_t lanes = __ballot(valid);
-    if (lanes == 0ull) return;
+    if (__ballot(any) == 0ull) return;
 
     int stk0 = 0, stk1 = 0;
     int sp = 0;
@@ -85,7 +93,8 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
             for (int i = 0; i < 32; ++i) w[i] = np[i];
             if (STATS) {
                 ts.node_wave += 1;
-                ts.node_lane += valid ? 1 : 0;
+                ts.node_lane += n_valid;
+                ts.box_lane += 4 * n_valid;
             }
             const uint32_t counts = w[28];
             uint64_t hitmask[4];
@@ -94,18 +103,19 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
                 const float lox = __uint_as_float(w[k]), hix = __uint_as_float(w[4 + k]);
                 const float loy = __uint_as_float(w[8 + k]), hiy = __uint_as_float(w[12 + k]);
                 const float loz = __uint_as_float(w[16 + k]), hiz = __uint_as_float(w[20 + k]);
-                const int32_t ch = (int32_t)w[24 + k];
-                const uint32_t cnt = (counts >> (8 * k)) & 255u;
-                float tx0 = (lox - o[0]) * inv[0], tx1 = (hix - o[0]) * inv[0];
-                float ty0 = (loy - o[1]) * inv[1], ty1 = (hiy - o[1]) * inv[1];
-                float tz0 = (loz - o[2]) * inv[2], tz1 = (hiz - o[2]) * inv[2];
-                float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near));
-                float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
-                bool slot = ch >= 0 || cnt > 0u;
-                bool h = valid && slot && t0 <= fminf(t1, t_best);
-                hitmask[k] = __ballot(h);
+                const bool slot = (int32_t)w[24 + k] >= 0 || ((counts >> (8 * k)) & 255u) != 0u;
+                bool h = false;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    float tx0 = (lox - o[0]) * inv[r][0], tx1 = (hix - o[0]) * inv[r][0];
+                    float ty0 = (loy - o[1]) * inv[r][1], ty1 = (hiy - o[1]) * inv[r][1];
+                    float tz0 = (loz - o[2]) * inv[r][2], tz1 = (hiz - o[2]) * inv[r][2];
+                    float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near));
+                    float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
+                    h = h | (valid[r] & (t0 <= fminf(t1, t_best[r])));
+                }
+                hitmask[k] = __ballot(h & slot);
             }
-            if (STATS) ts.box_lane += 4 * (unsigned long long)(valid ? 1 : 0);
             const uint64_t ord = ((uint64_t)w[30] << 32) | w[29];
             const uint32_t byte = (uint32_t)(ord >> (8 * oct)) & 255u;
             // push hit children far-to-near so the nearest is on top
@@ -141,7 +151,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
             for (int i = 0; i < 12 * kLeafMax; ++i) tw[i] = tp[i];
             if (STATS) {
                 ts.tri_wave += cnt;
-                ts.tri_lane += valid ? cnt : 0;
+                ts.tri_lane += cnt * n_valid;
             }
 #pragma unroll
             for (int j = 0; j < kLeafMax; ++j) {
@@ -151,22 +161,28 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
                 const int32_t id = (int32_t)w3[3];
                 const float e1x = __uint_as_float(w3[4]), e1y = __uint_as_float(w3[5]), e1z = __uint_as_float(w3[6]);
                 const float e2x = __uint_as_float(w3[8]), e2y = __uint_as_float(w3[9]), e2z = __uint_as_float(w3[10]);
-                float px = d[1] * e2z - d[2] * e2y;
-                float py = d[2] * e2x - d[0] * e2z;
-                float pz = d[0] * e2y - d[1] * e2x;
-                float det = e1x * px + e1y * py + e1z * pz;
-                float sx = o[0] - v0x, sy = o[1] - v0y, sz = o[2] - v0z;
-                float qx = sy * e1z - sz * e1y;
-                float qy = sz * e1x - sx * e1z;
-                float qz = sx * e1y - sy * e1x;
-                float inv_det = __builtin_amdgcn_rcpf(det);
-                float u = (sx * px + sy * py + sz * pz) * inv_det;
-                float v = (d[0] * qx + d[1] * qy + d[2] * qz) * inv_det;
-                float t = (e2x * qx + e2y * qy + e2z * qz) * inv_det;
-                bool h = valid && det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t >= t_near;
-                bool take = h && (t < t_best || (t == t_best && (id_best < 0 || id < id_best)));
-                t_best = take ? t : t_best;
-                id_best = take ? id : id_best;
+                // S = o - v0 and Q = S x e1 do not depend on the ray direction: shared by the lane's rays
+                const float sx = o[0] - v0x, sy = o[1] - v0y, sz = o[2] - v0z;
+                const float qx = sy * e1z - sz * e1y;
+                const float qy = sz * e1x - sx * e1z;
+                const float qz = sx * e1y - sy * e1x;
+                const float tq = e2x * qx + e2y * qy + e2z * qz;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const float* dr = d[r];
+                    float px = dr[1] * e2z - dr[2] * e2y;
+                    float py = dr[2] * e2x - dr[0] * e2z;
+                    float pz = dr[0] * e2y - dr[1] * e2x;
+                    float det = e1x * px + e1y * py + e1z * pz;
+                    float inv_det = __builtin_amdgcn_rcpf(det);
+                    float u = (sx * px + sy * py + sz * pz) * inv_det;
+                    float v = (dr[0] * qx + dr[1] * qy + dr[2] * qz) * inv_det;
+                    float t = tq * inv_det;
+                    bool h = valid[r] && det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t >= t_near;
+                    bool take = h && (t < t_best[r] || (t == t_best[r] && (id_best[r] < 0 || id < id_best[r])));
+                    t_best[r] = take ? t : t_best[r];
+                    id_best[r] = take ? id : id_best[r];
+                }
             }
         }
         if (sp == 0) break;
@@ -174,7 +190,53 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, bool valid, co
         entry = sp < 64 ? __builtin_amdgcn_readlane(stk0, sp) : __builtin_amdgcn_readlane(stk1, sp - 64);
     }
     if (overflow && lane_id() == 0) atomicOr(err, kErrStack);
-    if (STATS) ts.hits += (id_best >= 0) ? 1 : 0;
+    if (STATS)
+        for (int r = 0; r < NR; ++r) ts.hits += (valid[r] && id_best[r] >= 0) ? 1 : 0;
+}
+
+// Swarm members of the view's swarm (other than the agent itself) as boxes turned with their attitude:
+// slab test in each member's body frame, entry depth in [near, far]; a member at the same depth as the
+// mesh hit leaves the mesh hit, and earlier members win ties (their ids are lower).
+template <int NR>
+__device__ __forceinline__ void trace_members(const RenderArgs& a, const vf_view& vw, int64_t self, int32_t n_tris,
+                                              const bool (&valid)[NR], const float o[3], const float (&d)[NR][3],
+                                              float (&t_best)[NR], int32_t (&id_best)[NR]) {
+    if (vw.swarm < 0 || vw.swarm > a.swarm.n) {
+        if (lane_id() == 0) atomicOr(a.err, kErrView);
+        return;
+    }
+    const int b = a.swarm.off[vw.swarm - 1], e = a.swarm.off[vw.swarm];
+    for (int j = b; j < e; ++j) {
+        const int64_t ms = a.swarm.slots[j];
+        if (ms == self) continue;
+        if (ms < 0 || ms >= a.n_slots) {
+            if (lane_id() == 0) atomicOr(a.err, kErrSlot);
+            continue;
+        }
+        const float* mp = a.state + ms * 17;
+        float r[9];
+        quat_rot(mp + 3, r);
+        // o' = R^T (o - c)
+        const float dx = o[0] - mp[0], dy = o[1] - mp[1], dz = o[2] - mp[2];
+        float ob[3];
+        for (int k = 0; k < 3; ++k) ob[k] = r[k] * dx + r[3 + k] * dy + r[6 + k] * dz;
+        const int32_t id = n_tris + (j - b);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            float t_in = -INFINITY, t_out = INFINITY;
+            for (int ax = 0; ax < 3; ++ax) {
+                const float db = r[ax] * d[k][0] + r[3 + ax] * d[k][1] + r[6 + ax] * d[k][2];
+                const float inv = safe_inv(db);
+                const float t1 = (-a.swarm.half[ax] - ob[ax]) * inv, t2 = (a.swarm.half[ax] - ob[ax]) * inv;
+                t_in = fmaxf(t_in, fminf(t1, t2));
+                t_out = fminf(t_out, fmaxf(t1, t2));
+            }
+            const bool take = valid[k] && t_in <= t_out && t_in >= vw.near_clip &&
+                              (t_in < t_best[k] || (t_in == t_best[k] && id_best[k] < 0));
+            t_best[k] = take ? t_in : t_best[k];
+            id_best[k] = take ? id : id_best[k];
+        }
+    }
 }
 
 // Validate an agent's view; returns false (and flags the error) if it cannot be rendered.
@@ -198,8 +260,9 @@ k_render(RenderArgs a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
     const int g = logical_group(a.total_groups);
-    const int agent = g / a.groups_per_agent;
-    const int group = g - agent * a.groups_per_agent;
+    const int la = g / a.groups_per_agent;
+    const int group = g - la * a.groups_per_agent;
+    const int agent = a.order ? a.order[la] : la;
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
 
@@ -232,33 +295,50 @@ k_render(RenderArgs a) {
     __syncthreads();
     if (!ok_shared) return;
 
-    const int tiles_x = (vw.W + kTile - 1) / kTile;
-    const int tiles_y = (vw.H + kTile - 1) / kTile;
+    // the wavefront's packet: kPacketRows x kPacketCols 8x8 sub-tiles, one ray of each per lane
+    constexpr int NR = kPacketRows * kPacketCols;
+    const int th = kTile * kPacketRows, tw_ = kTile * kPacketCols;
+    const int tiles_x = (vw.W + tw_ - 1) / tw_;
+    const int tiles_y = (vw.H + th - 1) / th;
     const int tile = group * kWavesPerBlock + wave;
     if (tile >= tiles_x * tiles_y) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int r = ty * kTile + (lane >> 3), c = tx * kTile + (lane & 7);
-    const bool valid = r < vw.H && c < vw.W;
+    int row[NR], col[NR];
+    bool valid[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        row[k] = ty * th + (k / kPacketCols) * kTile + (lane >> 3);
+        col[k] = tx * tw_ + (k % kPacketCols) * kTile + (lane & 7);
+        valid[k] = row[k] < vw.H && col[k] < vw.W;
+    }
 
-    float rot[9];
-    quat_rot(pose + 3, rot);
-    float o[3] = {pose[0], pose[1], pose[2]};
-    float d[3];
-    pixel_ray(rot, tanf(0.5f * vw.hfov), vw.H, vw.W, r, c, d);
+    float rot[9], o[3];
+    camera_pose(pose, vw, o, rot);
+    float d[NR][3];
+    const float tan_h = tanf(0.5f * vw.hfov);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) pixel_ray(rot, tan_h, vw.H, vw.W, row[k], col[k], d[k]);
     const SceneDesc sc = a.scenes[vw.scene_id];
-    float t_best;
-    int32_t id_best;
+    float t_best[NR];
+    int32_t id_best[NR];
     TraceStats ts = {0, 0, 0, 0, 0, 0};
-    trace_packet<STATS>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts);
-    if (valid) {
-        int64_t pix = vw.out_offset + (int64_t)r * vw.W + c;
-        if (a.depth) a.depth[pix] = id_best >= 0 ? t_best : vw.miss_depth;
-        if (a.tri_id) a.tri_id[pix] = id_best;
+    trace_packet<NR, STATS>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts);
+    if (vw.swarm != 0) trace_members<NR>(a, vw, slot, sc.n_tris, valid, o, d, t_best, id_best);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (!valid[k]) continue;
+        int64_t pix = vw.out_offset + (int64_t)row[k] * vw.W + col[k];
+        if (a.depth) a.depth[pix] = id_best[k] >= 0 ? t_best[k] : vw.miss_depth;
+        if (a.tri_id) a.tri_id[pix] = id_best[k];
         if (a.rgb) {
             int64_t plane = (int64_t)vw.H * vw.W;
-            uint8_t* dst = a.rgb + 3 * vw.out_offset + (int64_t)r * vw.W + c;
-            if (id_best >= 0 && sc.rgb) {
-                const uint8_t* src = sc.rgb + 3 * (int64_t)id_best;
+            uint8_t* dst = a.rgb + 3 * vw.out_offset + (int64_t)row[k] * vw.W + col[k];
+            if (id_best[k] >= sc.n_tris) {
+                dst[0] = a.swarm.rgb[0];
+                dst[plane] = a.swarm.rgb[1];
+                dst[2 * plane] = a.swarm.rgb[2];
+            } else if (id_best[k] >= 0 && sc.rgb) {
+                const uint8_t* src = sc.rgb + 3 * (int64_t)id_best[k];
                 dst[0] = src[0];
                 dst[plane] = src[1];
                 dst[2 * plane] = src[2];
@@ -272,7 +352,8 @@ k_render(RenderArgs a) {
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
         unsigned long long v[6] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits};
-        unsigned long long rays = valid ? 1 : 0;
+        unsigned long long rays = 0;
+        for (int k = 0; k < NR; ++k) rays += valid[k] ? 1 : 0;
         for (int off = 32; off > 0; off >>= 1) {
             for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], off);
             rays += __shfl_xor(rays, off);
@@ -329,9 +410,108 @@ hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n,
     return hipGetLastError();
 }
 
+// Spatial order of a batch (one workgroup): key = scene id, then a 2-D Morton code of the position on a
+// 1024 x 1024 grid over the batch's own bounds; bitonic sort of (key, index) in LDS.  Consecutive
+// logical agents -- and so the agents one XCD renders -- then share a scene region, which keeps the
+// part of the BVH each XCD touches small enough for its L2.  The order changes which workgroup renders
+// an agent, never what it renders.
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__global__ void __launch_bounds__(1024) k_order(OrderArgs a) {
+    __shared__ unsigned long long keys[kOrderMax];
+    __shared__ float red[4][32];
+    const int t = threadIdx.x;
+    // bounds of the positions
+    float lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY;
+    for (int i = t; i < a.n; i += blockDim.x) {
+        int64_t slot = a.env_idx ? (int64_t)a.env_idx[i] : (int64_t)i;
+        if (slot < 0 || slot >= a.n_slots) continue;
+        float x = a.state[slot * 17], y = a.state[slot * 17 + 1];
+        lx = fminf(lx, x);
+        ly = fminf(ly, y);
+        hx = fmaxf(hx, x);
+        hy = fmaxf(hy, y);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, off));
+        ly = fminf(ly, __shfl_xor(ly, off));
+        hx = fmaxf(hx, __shfl_xor(hx, off));
+        hy = fmaxf(hy, __shfl_xor(hy, off));
+    }
+    const int w = t >> 6, nw = blockDim.x >> 6;
+    if ((t & 63) == 0) {
+        red[0][w] = lx;
+        red[1][w] = ly;
+        red[2][w] = hx;
+        red[3][w] = hy;
+    }
+    __syncthreads();
+    lx = red[0][0];
+    ly = red[1][0];
+    hx = red[2][0];
+    hy = red[3][0];
+    for (int k = 1; k < nw; ++k) {
+        lx = fminf(lx, red[0][k]);
+        ly = fminf(ly, red[1][k]);
+        hx = fmaxf(hx, red[2][k]);
+        hy = fmaxf(hy, red[3][k]);
+    }
+    const float sx = hx > lx ? 1023.0f / (hx - lx) : 0.0f, sy = hy > ly ? 1023.0f / (hy - ly) : 0.0f;
+    int m = 1;
+    while (m < a.n) m <<= 1;
+    for (int i = t; i < m; i += blockDim.x) {
+        unsigned long long key = ~0ull;
+        if (i < a.n) {
+            int64_t slot = a.env_idx ? (int64_t)a.env_idx[i] : (int64_t)i;
+            uint32_t code = 0xFFFFFFFFu;
+            if (slot >= 0 && slot < a.n_slots) {
+                float x = a.state[slot * 17], y = a.state[slot * 17 + 1];
+                uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), 1023.0f);
+                uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), 1023.0f);
+                uint32_t sid = (uint32_t)a.views[i].scene_id & 1023u;
+                code = (sid << 20) | spread10(cx) | (spread10(cy) << 1);
+            }
+            key = ((unsigned long long)code << 32) | (uint32_t)i;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < m; i += blockDim.x) {
+                int l = i ^ j;
+                if (l > i) {
+                    unsigned long long x = keys[i], y = keys[l];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        keys[i] = y;
+                        keys[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < a.n; i += blockDim.x) a.order[i] = (int32_t)(uint32_t)keys[i];
+}
+
+hipError_t launch_order(const OrderArgs& a, hipStream_t st) {
+    if (a.n <= 0 || a.n > kOrderMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    int tiles = ((a.max_h + kTile - 1) / kTile) * ((a.max_w + kTile - 1) / kTile);
+    const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
+    int tiles = ((a.max_h + th - 1) / th) * ((a.max_w + tw - 1) / tw);
     a.groups_per_agent = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     int64_t total = (int64_t)a.n * a.groups_per_agent;
     if (total > 0x7fffffff) return hipErrorInvalidValue;

@@ -54,7 +54,8 @@ bool check_dyn_params(const vf_dyn_params& p, std::string* why) {
     if (!pos(p.dt)) return *why = "dt must be > 0", false;
     if (p.n_sub < 1 || p.n_sub > 1024) return *why = "n_sub must be in [1, 1024]", false;
     if (p.integrator != VF_RK4 && p.integrator != VF_EULER) return *why = "integrator must be VF_RK4 or VF_EULER", false;
-    if (p.ctrl != VF_CTBR && p.ctrl != VF_SRT) return *why = "ctrl must be VF_CTBR or VF_SRT", false;
+    if (p.ctrl != VF_CTBR && p.ctrl != VF_SRT && p.ctrl != VF_PS && p.ctrl != VF_LV)
+        return *why = "ctrl must be VF_CTBR, VF_SRT, VF_PS or VF_LV", false;
     if (!pos(p.mass) || !pos(p.arm) || !pos(p.tau_motor) || !pos(p.kappa_yaw) || !pos(p.f_max))
         return *why = "mass, arm, tau_motor, kappa_yaw and f_max must be > 0", false;
     for (int i = 0; i < 3; ++i) {
@@ -63,6 +64,13 @@ bool check_dyn_params(const vf_dyn_params& p, std::string* why) {
             return *why = "drag and rate gains must be finite", false;
     }
     if (!fin(p.g)) return *why = "g must be finite", false;
+    if (p.ctrl == VF_PS || p.ctrl == VF_LV) {
+        if (!(p.g > 0.f)) return *why = "PS / LV need g > 0", false;
+        for (int i = 0; i < 3; ++i)
+            if (!fin(p.k_pos[i]) || !fin(p.k_vel[i]) || !fin(p.k_att[i]))
+                return *why = "PS / LV gains must be finite", false;
+        if (!(p.max_tilt > 0.f && p.max_tilt < 1.5707f)) return *why = "max_tilt must be in (0, pi/2)", false;
+    }
     return true;
 }
 
@@ -90,15 +98,27 @@ DynConst make_dyn_const(const vf_dyn_params& p) {
     double h = (double)p.dt / (double)p.n_sub;
     c.e_half = (float)exp(-0.5 * h / (double)p.tau_motor);
     c.e_full = (float)exp(-h / (double)p.tau_motor);
+    for (int i = 0; i < 3; ++i) {
+        c.k_pos[i] = p.k_pos[i];
+        c.k_vel[i] = p.k_vel[i];
+        c.k_att[i] = p.k_att[i];
+    }
+    c.tan_tilt = (float)tan((double)p.max_tilt);
+    c.min_lift = (float)(0.25 * (double)p.g);
     return c;
 }
 
 static vf_status sync_scene_table(vf_ctx* ctx) {
     std::vector<SceneDesc> tab(kMaxScenes);
+    std::vector<const int32_t*> lab(kMaxScenes, nullptr);
     memset(tab.data(), 0, sizeof(SceneDesc) * kMaxScenes);
     for (size_t i = 0; i < ctx->scenes.size(); ++i)
-        if (ctx->scenes[i].used) tab[i] = ctx->scenes[i].desc;
+        if (ctx->scenes[i].used) {
+            tab[i] = ctx->scenes[i].desc;
+            lab[i] = ctx->scenes[i].labels;
+        }
     VF_HIP(hipMemcpy(ctx->d_scenes, tab.data(), sizeof(SceneDesc) * kMaxScenes, hipMemcpyHostToDevice));
+    VF_HIP(hipMemcpy(ctx->d_labels, lab.data(), sizeof(void*) * kMaxScenes, hipMemcpyHostToDevice));
     return VF_OK;
 }
 
@@ -153,6 +173,9 @@ vf_status vf_create(int device, size_t hbm_budget_bytes, vf_ctx** out) {
     vf_status s = ctx_alloc(ctx, &p, sizeof(SceneDesc) * kMaxScenes);
     if (s != VF_OK) { delete ctx; return s; }
     ctx->d_scenes = (SceneDesc*)p;
+    s = ctx_alloc(ctx, &p, sizeof(void*) * kMaxScenes);
+    if (s != VF_OK) { ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes); delete ctx; return s; }
+    ctx->d_labels = (const int32_t**)p;
     s = ctx_alloc(ctx, &p, 256);
     if (s != VF_OK) { ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes); delete ctx; return s; }
     ctx->d_err = (uint32_t*)p;
@@ -170,9 +193,15 @@ vf_status vf_destroy(vf_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto& s : ctx->scenes)
-        if (s.used) ctx_free(ctx, s.block, s.bytes);
+        if (s.used) {
+            ctx_free(ctx, s.block, s.bytes);
+            if (s.labels) ctx_free(ctx, s.labels, s.label_bytes);
+        }
     for (auto& c : ctx->counters) ctx_free(ctx, c.counters, c.capacity * 4);
     ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes);
+    ctx_free(ctx, (void*)ctx->d_labels, sizeof(void*) * kMaxScenes);
+    if (ctx->swarm_bytes) ctx_free(ctx, (void*)ctx->swarm.off, ctx->swarm_bytes);
+    for (auto& o : ctx->orders) ctx_free(ctx, o.second, kOrderMax * 4);
     ctx_free(ctx, ctx->d_err, 256);
     delete ctx;
     return VF_OK;
@@ -221,6 +250,7 @@ vf_status vf_scene_free(vf_ctx* ctx, int32_t scene_id) {
     s.used = false;
     vf_status st = sync_scene_table(ctx);
     ctx_free(ctx, s.block, s.bytes);
+    if (s.labels) ctx_free(ctx, s.labels, s.label_bytes);
     s = SceneHost();
     return st;
 }
@@ -269,6 +299,30 @@ static vf_status check_render_common(vf_ctx* ctx, int64_t n, const float* state,
     return VF_OK;
 }
 
+// Agent order scratch of a stream (one per stream, so concurrent streams never share it).
+static int32_t* order_for(vf_ctx* ctx, hipStream_t st) {
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto& o : ctx->orders)
+            if (o.first == (void*)st) return o.second;
+    }
+    void* p = nullptr;
+    if (ctx_alloc(ctx, &p, kOrderMax * 4) != VF_OK) return nullptr;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->orders.push_back({(void*)st, (int32_t*)p});
+    return (int32_t*)p;
+}
+
+// Put a batch in spatial order before its render (batches of 64 .. kOrderMax agents).
+static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
+    a.order = nullptr;
+    if (!ctx->spatial_order || a.n < 64 || a.n > kOrderMax) return;
+    int32_t* buf = order_for(ctx, st);
+    if (!buf) return;   // no memory for the scratch: identity order
+    OrderArgs o{a.n, a.env_idx, a.state, a.n_slots, a.views, buf};
+    if (launch_order(o, st) == hipSuccess) a.order = buf;
+}
+
 static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_idx, float* state, int64_t n_slots,
                                    const vf_view* views, int32_t max_h, int32_t max_w, float* depth, int32_t* tri_id,
                                    uint8_t* rgb, int64_t out_pixels) {
@@ -289,6 +343,7 @@ static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_id
     a.out_pixels = out_pixels;
     a.err = ctx->d_err;
     a.stats = ctx->d_stats;
+    a.swarm = ctx->swarm;
     return a;
 }
 
@@ -315,13 +370,16 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
                                     out_pixels);
     bool split = ctx->launch_mode == VF_LAUNCH_SPLIT;
     if (ctx->launch_mode == VF_LAUNCH_AUTO) {
-        int64_t tiles = (int64_t)((max_h + kTile - 1) / kTile) * ((max_w + kTile - 1) / kTile);
+        const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
+        int64_t tiles = (int64_t)((max_h + th - 1) / th) * ((max_w + tw - 1) / tw);
         int64_t groups = n * ((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
         split = groups > 1024;
     }
+    if (ctx->swarm.n > 0) split = true;   // members must be read after every agent has stepped
     if (split) {
         StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
         VF_HIP(launch_step(sa, st));
+        maybe_order(ctx, a, st);
         VF_HIP(launch_render(a, false, ctx->stats, st));
         return VF_OK;
     }
@@ -345,6 +403,7 @@ vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float*
     VF_HIP(hipSetDevice(ctx->device));
     RenderArgs a = make_render_args(ctx, n, env_idx, (float*)state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
                                     out_pixels);
+    maybe_order(ctx, a, (hipStream_t)stream);
     VF_HIP(launch_render(a, false, ctx->stats, (hipStream_t)stream));
     return VF_OK;
 }
@@ -358,6 +417,8 @@ vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, 
         return fail(VF_EINVAL, "vf_step_backward: NULL array");
     std::string why;
     if (!check_dyn_params(*params, &why)) return fail(VF_EINVAL, "vf_step_backward: " + why);
+    if (params->ctrl != VF_CTBR && params->ctrl != VF_SRT)
+        return fail(VF_EINVAL, "vf_step_backward: the adjoint covers the CTBR and SRT controllers");
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
     StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action, make_dyn_const(*params)};
@@ -382,6 +443,82 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
     return VF_OK;
 }
 
+vf_status vf_sensor_noise(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
+                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb,
+                          int64_t out_pixels, void* stream) {
+    if (!ctx || !noise) return fail(VF_EINVAL, "vf_sensor_noise: NULL argument");
+    if (n < 0 || n > (1 << 24)) return fail(VF_EINVAL, "vf_sensor_noise: n must be in [0, 2^24]");
+    if (n > 0 && !views) return fail(VF_EINVAL, "vf_sensor_noise: views is NULL");
+    if (max_h < 1 || max_w < 1 || max_h > kMaxImage || max_w > kMaxImage)
+        return fail(VF_EINVAL, "vf_sensor_noise: max_h/max_w must be in [1, 1024]");
+    auto model_ok = [](int32_t m) { return m >= VF_NOISE_NONE && m <= VF_NOISE_SALT_PEPPER; };
+    if (!model_ok(noise->depth_model) || !model_ok(noise->rgb_model)) return fail(VF_EINVAL, "vf_sensor_noise: bad model");
+    if (!(noise->depth_sigma >= 0.f) || !(noise->rgb_sigma >= 0.f) || !(noise->depth_p >= 0.f && noise->depth_p <= 1.f) ||
+        !(noise->rgb_p >= 0.f && noise->rgb_p <= 1.f))
+        return fail(VF_EINVAL, "vf_sensor_noise: sigma must be >= 0 and p in [0, 1]");
+    if (n == 0) return VF_OK;
+    VF_HIP(hipSetDevice(ctx->device));
+    NoiseArgs a{(int32_t)n, views, max_h, max_w, 0, *noise, tri_id, depth, rgb, out_pixels, ctx->d_err};
+    VF_HIP(launch_noise(a, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_scene_set_labels(vf_ctx* ctx, int32_t scene_id, const int32_t* labels) {
+    if (!ctx) return fail(VF_EINVAL, "vf_scene_set_labels: NULL context");
+    if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].used)
+        return fail(VF_ENOSCENE, "vf_scene_set_labels: no such scene");
+    VF_HIP(hipSetDevice(ctx->device));
+    SceneHost& s = ctx->scenes[scene_id];
+    VF_HIP(hipDeviceSynchronize());
+    if (s.labels) {
+        ctx_free(ctx, s.labels, s.label_bytes);
+        s.labels = nullptr;
+        s.label_bytes = 0;
+    }
+    if (labels) {
+        void* p = nullptr;
+        int64_t bytes = s.info.n_tris * 4;
+        vf_status st = ctx_alloc(ctx, &p, bytes);
+        if (st != VF_OK) return st;
+        VF_HIP(hipMemcpy(p, labels, bytes, hipMemcpyDeviceToDevice));
+        s.labels = (int32_t*)p;
+        s.label_bytes = bytes;
+    }
+    return sync_scene_table(ctx);
+}
+
+vf_status vf_segmentation(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
+                          const int32_t* tri_id, int32_t* seg, int64_t out_pixels, void* stream) {
+    if (!ctx) return fail(VF_EINVAL, "vf_segmentation: NULL context");
+    if (n < 0 || n > (1 << 24)) return fail(VF_EINVAL, "vf_segmentation: n must be in [0, 2^24]");
+    if (n > 0 && (!views || !tri_id || !seg)) return fail(VF_EINVAL, "vf_segmentation: NULL array");
+    if (max_h < 1 || max_w < 1 || max_h > kMaxImage || max_w > kMaxImage)
+        return fail(VF_EINVAL, "vf_segmentation: max_h/max_w must be in [1, 1024]");
+    if (n == 0) return VF_OK;
+    VF_HIP(hipSetDevice(ctx->device));
+    SegArgs a{ctx->d_scenes, ctx->d_labels, (int32_t)ctx->scenes.size(), (int32_t)n, views, max_h, max_w, 0,
+              tri_id, seg, out_pixels, ctx->d_err};
+    VF_HIP(launch_segment(a, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_imu(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int32_t* env_idx, const float* state,
+                 int64_t n_slots, float sigma_acc, float sigma_gyro, uint64_t seed, const int32_t* keys, float* out,
+                 void* stream) {
+    if (!ctx || !params) return fail(VF_EINVAL, "vf_imu: NULL argument");
+    if (n < 0 || n > (1 << 24)) return fail(VF_EINVAL, "vf_imu: n must be in [0, 2^24]");
+    if (n > 0 && (!state || !out || n_slots < 1)) return fail(VF_EINVAL, "vf_imu: NULL array or empty table");
+    if (!(sigma_acc >= 0.f) || !(sigma_gyro >= 0.f)) return fail(VF_EINVAL, "vf_imu: sigma must be >= 0");
+    std::string why;
+    if (!check_dyn_params(*params, &why)) return fail(VF_EINVAL, "vf_imu: " + why);
+    if (n == 0) return VF_OK;
+    VF_HIP(hipSetDevice(ctx->device));
+    ImuArgs a{(int32_t)n, env_idx, state, n_slots, sigma_acc, sigma_gyro, seed, keys, out, ctx->d_err,
+              make_dyn_const(*params)};
+    VF_HIP(launch_imu(a, (hipStream_t)stream));
+    return VF_OK;
+}
+
 vf_status vf_closest_point(vf_ctx* ctx, int64_t n, const float* points, const int32_t* scene_ids, int32_t scene_id0,
                            float max_dist, float* dist, float* closest, int32_t* tri_id, void* stream) {
     if (!ctx) return fail(VF_EINVAL, "vf_closest_point: NULL context");
@@ -393,8 +530,81 @@ vf_status vf_closest_point(vf_ctx* ctx, int64_t n, const float* points, const in
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
     QueryArgs q{ctx->d_scenes, (int32_t)ctx->scenes.size(), (int32_t)n, points, scene_ids, scene_id0, max_dist, dist,
-                closest, tri_id, ctx->d_err};
+                closest, tri_id, ctx->d_err, nullptr, nullptr, 0, nullptr, 0.0f, nullptr, nullptr, SwarmTable{}};
     VF_HIP(launch_closest_point(q, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_collision(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float* state, int64_t n_slots,
+                       const vf_view* views, float radius, float max_dist, float* dist, float* rel, uint8_t* collided,
+                       void* stream) {
+    if (!ctx) return fail(VF_EINVAL, "vf_collision: NULL context");
+    if (n < 0 || n > (1 << 26)) return fail(VF_EINVAL, "vf_collision: n must be in [0, 2^26]");
+    if (n > 0 && (!state || !views || !dist || n_slots < 1)) return fail(VF_EINVAL, "vf_collision: NULL array");
+    if (!(max_dist > 0.0f) || !(radius >= 0.0f)) return fail(VF_EINVAL, "vf_collision: need max_dist > 0, radius >= 0");
+    if (n == 0) return VF_OK;
+    VF_HIP(hipSetDevice(ctx->device));
+    QueryArgs q{ctx->d_scenes, (int32_t)ctx->scenes.size(), (int32_t)n, nullptr, nullptr, 0, max_dist, dist,
+                nullptr, nullptr, ctx->d_err, state, env_idx, n_slots, views, radius, rel, collided, ctx->swarm};
+    VF_HIP(launch_closest_point(q, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, const int32_t* slots,
+                        const float half_extent[3], const uint8_t rgb[3]) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_swarms: NULL context");
+    if (n_swarms < 0 || n_swarms > (1 << 20)) return fail(VF_EINVAL, "vf_set_swarms: n_swarms must be in [0, 2^20]");
+    if (n_swarms > 0 && (!offsets || !half_extent || !rgb)) return fail(VF_EINVAL, "vf_set_swarms: NULL argument");
+    int64_t total = 0;
+    if (n_swarms > 0) {
+        if (offsets[0] != 0) return fail(VF_EINVAL, "vf_set_swarms: offsets[0] must be 0");
+        for (int32_t s = 0; s < n_swarms; ++s)
+            if (offsets[s + 1] < offsets[s]) return fail(VF_EINVAL, "vf_set_swarms: offsets must not decrease");
+        total = offsets[n_swarms];
+        if (total > 0 && !slots) return fail(VF_EINVAL, "vf_set_swarms: slots is NULL");
+        for (int64_t j = 0; j < total; ++j)
+            if (slots[j] < 0) return fail(VF_EINVAL, "vf_set_swarms: negative slot");
+        for (int k = 0; k < 3; ++k)
+            if (!(half_extent[k] > 0.f) || !isfinite(half_extent[k]))
+                return fail(VF_EINVAL, "vf_set_swarms: half extents must be > 0");
+    }
+    VF_HIP(hipSetDevice(ctx->device));
+    VF_HIP(hipDeviceSynchronize());
+    if (ctx->swarm_bytes) {
+        ctx_free(ctx, (void*)ctx->swarm.off, ctx->swarm_bytes);
+        ctx->swarm = SwarmTable{};
+        ctx->swarm_bytes = 0;
+    }
+    if (n_swarms == 0) return VF_OK;
+    const int64_t off_bytes = (int64_t)(n_swarms + 1) * 4;
+    const int64_t bytes = ((off_bytes + 255) / 256) * 256 + std::max<int64_t>(total, 1) * 4;
+    void* p = nullptr;
+    vf_status st = ctx_alloc(ctx, &p, bytes);
+    if (st != VF_OK) return st;
+    char* base = (char*)p;
+    int32_t* d_off = (int32_t*)base;
+    int32_t* d_slots = (int32_t*)(base + ((off_bytes + 255) / 256) * 256);
+    VF_HIP(hipMemcpy(d_off, offsets, off_bytes, hipMemcpyHostToDevice));
+    if (total > 0) VF_HIP(hipMemcpy(d_slots, slots, total * 4, hipMemcpyHostToDevice));
+    SwarmTable t{};
+    t.off = d_off;
+    t.slots = d_slots;
+    t.n = n_swarms;
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        t.half[k] = half_extent[k];
+        r2 += (double)half_extent[k] * half_extent[k];
+    }
+    t.radius = (float)sqrt(r2);
+    for (int k = 0; k < 3; ++k) t.rgb[k] = rgb[k];
+    ctx->swarm = t;
+    ctx->swarm_bytes = bytes;
+    return VF_OK;
+}
+
+vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_spatial_order: NULL context");
+    ctx->spatial_order = enable != 0;
     return VF_OK;
 }
 

@@ -18,7 +18,15 @@ namespace vf {
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
-constexpr int kWavesPerBlock = 4;     // render workgroup = 4 wavefronts = 4 tiles
+constexpr int kWavesPerBlock = 4;     // render workgroup = 4 wavefronts = 4 packets
+#ifndef VF_PACKET_ROWS
+#define VF_PACKET_ROWS 1
+#endif
+#ifndef VF_PACKET_COLS
+#define VF_PACKET_COLS 1
+#endif
+constexpr int kPacketRows = VF_PACKET_ROWS;  // a wavefront's packet: rows x cols of 8x8 tiles,
+constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 #ifndef VF_LEAF_MAX
 #define VF_LEAF_MAX 4
 #endif
@@ -72,6 +80,9 @@ struct alignas(16) SceneDesc {
     int32_t pad[5];
 };
 static_assert(sizeof(SceneDesc) == 64, "scene table entry is 64 bytes");
+static_assert(sizeof(vf_view) == 72, "view descriptor is 72 bytes");
+static_assert(sizeof(vf_dyn_params) == 128, "parameter block is 128 bytes");
+static_assert(sizeof(vf_noise) == 32, "noise block is 32 bytes");
 
 // ---------------------------------------------------------------------------
 // dynamics constants, derived once per call on the host
@@ -86,6 +97,8 @@ struct DynConst {
     float kappa, inv_kappa, f_max;
     float k_lin[3], c_quad[3];
     float e_half, e_full; // exp(-h / (2 tau)), exp(-h / tau)
+    float k_pos[3], k_vel[3], k_att[3];
+    float tan_tilt, min_lift;   // tan(max_tilt), g / 4
 };
 
 DynConst make_dyn_const(const vf_dyn_params& p);
@@ -94,10 +107,22 @@ bool check_dyn_params(const vf_dyn_params& p, std::string* why);
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+// Swarm table: CSR lists of member state slots and the members' body box.
+struct SwarmTable {
+    const int32_t* off;     // [n + 1]
+    const int32_t* slots;   // [off[n]]
+    int32_t n;
+    float half[3];
+    float radius;           // |half|, the bounding-sphere radius used by the collision check
+    uint8_t rgb[4];
+};
+
 struct SceneHost {
     bool used = false;
     void* block = nullptr;      // one device allocation holding everything below
     int64_t bytes = 0;
+    int32_t* labels = nullptr;  // optional per-triangle semantic labels
+    int64_t label_bytes = 0;
     vf_scene_info info{};
     SceneDesc desc{};
 };
@@ -118,11 +143,16 @@ struct vf_ctx {
     std::mutex mu;
     std::vector<vf::SceneHost> scenes;
     vf::SceneDesc* d_scenes = nullptr;     // device scene table [kMaxScenes]
+    const int32_t** d_labels = nullptr;    // device table of per-scene label arrays [kMaxScenes]
     uint32_t* d_err = nullptr;             // sticky error word
     unsigned long long* d_stats = nullptr; // 8 counters
     bool stats = false;
     int32_t launch_mode = VF_LAUNCH_AUTO;
     std::vector<vf::Counters> counters;
+    vf::SwarmTable swarm{};                // device copy of the swarm lists (n = 0: none)
+    int64_t swarm_bytes = 0;
+    bool spatial_order = true;             // render agents in (scene, position) order
+    std::vector<std::pair<void*, int32_t*>> orders;   // per stream: [kOrderMax] agent order scratch
 };
 
 namespace vf {
@@ -148,8 +178,20 @@ struct RenderArgs {
     uint32_t* err;
     unsigned long long* stats;
     int32_t* counters;
+    const int32_t* order;    // logical agent -> view index (spatial order), or NULL for identity
+    SwarmTable swarm;
     DynConst dyn;
 };
+constexpr int kOrderMax = 4096;      // batches up to this size are put in spatial order
+struct OrderArgs {
+    int32_t n;
+    const int32_t* env_idx;
+    const float* state;
+    int64_t n_slots;
+    const vf_view* views;
+    int32_t* order;
+};
+hipError_t launch_order(const OrderArgs& a, hipStream_t st);
 struct StepArgs {
     int32_t n;
     const int32_t* env_idx;
@@ -181,6 +223,47 @@ struct RenderBackArgs {
     float* grad_state;
     uint32_t* err;
 };
+struct NoiseArgs {
+    int32_t n;
+    const vf_view* views;
+    int32_t max_h, max_w;
+    int32_t blocks_per_agent;
+    vf_noise cfg;
+    const int32_t* tri_id;
+    float* depth;
+    uint8_t* rgb;
+    int64_t out_pixels;
+    uint32_t* err;
+};
+struct SegArgs {
+    const SceneDesc* scenes;
+    const int32_t* const* labels;
+    int32_t n_scenes;
+    int32_t n;
+    const vf_view* views;
+    int32_t max_h, max_w;
+    int32_t blocks_per_agent;
+    const int32_t* tri_id;
+    int32_t* seg;
+    int64_t out_pixels;
+    uint32_t* err;
+};
+struct ImuArgs {
+    int32_t n;
+    const int32_t* env_idx;
+    const float* state;
+    int64_t n_slots;
+    float sigma_acc, sigma_gyro;
+    uint64_t seed;
+    const int32_t* keys;
+    float* out;
+    uint32_t* err;
+    DynConst dyn;
+};
+hipError_t launch_noise(NoiseArgs a, hipStream_t st);
+hipError_t launch_segment(SegArgs a, hipStream_t st);
+hipError_t launch_imu(const ImuArgs& a, hipStream_t st);
+
 struct QueryArgs {
     const SceneDesc* scenes;
     int32_t n_scenes;
@@ -193,6 +276,15 @@ struct QueryArgs {
     float* closest;
     int32_t* tri_id;
     uint32_t* err;
+    // agent mode (collision check): points are state rows, scenes come from the views
+    const float* state;
+    const int32_t* env_idx;
+    int64_t n_slots;
+    const vf_view* views;
+    float radius;
+    float* rel;
+    uint8_t* collided;
+    SwarmTable swarm;
 };
 hipError_t launch_closest_point(const QueryArgs& q, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, hipStream_t st);

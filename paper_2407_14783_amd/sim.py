@@ -34,10 +34,15 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_views(n, scene_ids, hw, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None, device="cuda"):
-    """Per-agent view array [n] on the device plus (out_pixels, offsets, max_h, max_w).
+def make_views(n, scene_ids, hw, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None, device="cuda",
+               noise_keys=None, mount_q=None, mount_t=None, swarm=None):
+    """Per-view array [n] on the device plus (out_pixels, offsets, max_h, max_w).
 
-    scene_ids: int or [n]; hw: (H, W) or [n, 2]; outputs are packed agent after agent.
+    scene_ids: int or [n]; hw: (H, W) or [n, 2]; outputs are packed view after view.
+    noise_keys: per-view sensor-noise key ([n] ints; default the view index).
+    mount_q / mount_t: camera orientation (w, x, y, z) and position in the body frame, [4] / [3] or
+    [n, 4] / [n, 3]; default no rotation, no offset.
+    swarm: per-view swarm index (int or [n]; -1 none) of the table given to Context.set_swarms.
     """
     scene_ids = np.broadcast_to(np.asarray(scene_ids, dtype=np.int64).reshape(-1), (n,))
     hw = np.broadcast_to(np.asarray(hw, dtype=np.int64).reshape(-1, 2), (n, 2))
@@ -49,6 +54,10 @@ def make_views(n, scene_ids, hw, hfov=np.pi / 2, near=0.01, far=100.0, miss_dept
     v["near_clip"] = near
     v["far_clip"] = far
     v["miss_depth"] = far if miss_depth is None else miss_depth
+    v["flags"] = np.arange(n) if noise_keys is None else np.broadcast_to(np.asarray(noise_keys), (n,))
+    v["mount_q"] = (1.0, 0.0, 0.0, 0.0) if mount_q is None else np.broadcast_to(np.asarray(mount_q), (n, 4))
+    v["mount_t"] = 0.0 if mount_t is None else np.broadcast_to(np.asarray(mount_t), (n, 3))
+    v["swarm"] = 0 if swarm is None else np.broadcast_to(np.asarray(swarm), (n,)) + 1
     px = hw[:, 0] * hw[:, 1]
     offsets = np.concatenate([[0], np.cumsum(px)[:-1]]).astype(np.int64)
     v["out_offset"] = offsets
@@ -160,6 +169,88 @@ class Context:
                                    _ptr(closest), _ptr(tri_id), _stream(stream)), "vf_closest_point")
         return dist
 
+    def collision(self, state, views, radius, n=None, env_idx=None, max_dist=1e30, rel=None, collided=None,
+                  stream=None):
+        """Nearest-obstacle distance [n] of each agent's position in its view's scene, with the offset to
+        that point (rel [n, 3], optional) and the contact flag dist <= radius (collided [n] uint8, optional)."""
+        n = state.shape[0] if n is None else n
+        _check_views(views, n)
+        if env_idx is not None and env_idx.numel() < n:
+            raise ValueError("env_idx holds fewer than n entries")
+        if env_idx is None:
+            _check_rows(state, n, 17, "state")
+        _check_rows(rel, n, 3, "rel")
+        _check_rows(collided, n, 1, "collided")
+        dist = torch.empty(n, dtype=torch.float32, device=state.device)
+        check(lib.vf_collision(self.h, n, _ptr(env_idx), _ptr(state), state.shape[0], _ptr(views), float(radius),
+                               float(max_dist), _ptr(dist), _ptr(rel), _ptr(collided), _stream(stream)),
+              "vf_collision")
+        return dist
+
+    def set_swarms(self, groups, half_extent=(0.15, 0.15, 0.05), rgb=(255, 64, 0)):
+        """Swarms as lists of state slots (agents that see each other); [] clears."""
+        offs = np.zeros(len(groups) + 1, dtype=np.int32)
+        offs[1:] = np.cumsum([len(g) for g in groups])
+        slots = np.concatenate([np.asarray(g, dtype=np.int32) for g in groups]) if groups else np.zeros(0, np.int32)
+        slots = np.ascontiguousarray(slots, dtype=np.int32)
+        half = (ctypes.c_float * 3)(*half_extent)
+        col = (ctypes.c_uint8 * 3)(*rgb)
+        check(lib.vf_set_swarms(self.h, len(groups), offs.ctypes.data_as(ctypes.c_void_p),
+                                slots.ctypes.data_as(ctypes.c_void_p), half, col), "vf_set_swarms")
+
+    # ---------------------------------------------------------------- sensors
+    def sensor_noise(self, views, n, max_hw, out_pixels, depth=None, rgb=None, tri_id=None,
+                     depth_model=capi.VF_NOISE_NONE, depth_sigma=0.0, depth_p=0.0, rgb_model=capi.VF_NOISE_NONE,
+                     rgb_sigma=0.0, rgb_p=0.0, seed=0, stream=None):
+        """Table II noise applied in place to rendered depth / planar rgb (keys from views' flags)."""
+        _check_views(views, n)
+        for t, c, nm in ((depth, 1, "depth"), (rgb, 3, "rgb"), (tri_id, 1, "tri_id")):
+            _check_rows(t, out_pixels, c, nm)
+        cfg = capi.Noise(int(depth_model), float(depth_sigma), float(depth_p), int(rgb_model), float(rgb_sigma),
+                         float(rgb_p), int(seed) & 0xFFFFFFFFFFFFFFFF)
+        check(lib.vf_sensor_noise(self.h, n, _ptr(views), int(max_hw[0]), int(max_hw[1]), ctypes.byref(cfg),
+                                  _ptr(tri_id), _ptr(depth), _ptr(rgb), int(out_pixels), _stream(stream)),
+              "vf_sensor_noise")
+
+    def set_labels(self, sid, labels):
+        """Per-triangle int32 semantic labels of a scene (None removes them)."""
+        if labels is None:
+            check(lib.vf_scene_set_labels(self.h, sid, None), "vf_scene_set_labels")
+            return
+        lab = torch.as_tensor(np.asarray(labels, dtype=np.int32)).cuda(self.device)
+        if lab.numel() != self.scene_info(sid)["n_tris"]:
+            raise ValueError("labels must hold one value per triangle")
+        check(lib.vf_scene_set_labels(self.h, sid, _ptr(lab)), "vf_scene_set_labels")
+
+    def segmentation(self, views, n, max_hw, tri_id, out_pixels, seg=None, stream=None):
+        _check_views(views, n)
+        _check_rows(tri_id, out_pixels, 1, "tri_id")
+        if seg is None:
+            seg = torch.empty(out_pixels, dtype=torch.int32, device=tri_id.device)
+        _check_rows(seg, out_pixels, 1, "seg")
+        check(lib.vf_segmentation(self.h, n, _ptr(views), int(max_hw[0]), int(max_hw[1]), _ptr(tri_id), _ptr(seg),
+                                  int(out_pixels), _stream(stream)), "vf_segmentation")
+        return seg
+
+    def imu(self, params, state, n=None, env_idx=None, sigma_acc=0.0, sigma_gyro=0.0, seed=0, keys=None,
+            out=None, stream=None):
+        """[n, 6] accelerometer (specific force, body frame) and gyro readings at the given states."""
+        p = params if isinstance(params, capi.DynParams) else capi.params_struct(params)
+        n = state.shape[0] if n is None else n
+        if env_idx is not None and env_idx.numel() < n:
+            raise ValueError("env_idx holds fewer than n entries")
+        if env_idx is None:
+            _check_rows(state, n, 17, "state")
+        if keys is not None and keys.numel() < n:
+            raise ValueError("keys holds fewer than n entries")
+        if out is None:
+            out = torch.empty((n, 6), dtype=torch.float32, device=state.device)
+        _check_rows(out, n, 6, "out")
+        check(lib.vf_imu(self.h, ctypes.byref(p), n, _ptr(env_idx), _ptr(state), state.shape[0], float(sigma_acc),
+                         float(sigma_gyro), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(keys), _ptr(out), _stream(stream)),
+              "vf_imu")
+        return out
+
     # ---------------------------------------------------------------- diagnostics
     def sync_check(self, stream=None):
         check(lib.vf_sync_check(self.h, _stream(stream)), "vf_sync_check")
@@ -168,6 +259,10 @@ class Context:
         """True: fused single launch; False: split; None: automatic by batch size (the default)."""
         mode = capi.VF_LAUNCH_AUTO if fused is None else (capi.VF_LAUNCH_FUSED if fused else capi.VF_LAUNCH_SPLIT)
         check(lib.vf_set_launch_mode(self.h, mode), "vf_set_launch_mode")
+
+    def set_spatial_order(self, on):
+        """Sort split-launch batches by (scene, position) before rendering (default on)."""
+        check(lib.vf_set_spatial_order(self.h, 1 if on else 0), "vf_set_spatial_order")
 
     def set_stats(self, on):
         check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")

@@ -32,8 +32,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     from paper_2407_14783_amd import capi
-    assert ctypes.sizeof(capi.DynParams) == 88
-    assert capi.VIEW_DTYPE.itemsize == 40 and capi.VIEW_DTYPE.fields["out_offset"][1] == 32
+    assert ctypes.sizeof(capi.DynParams) == 128
+    assert capi.VIEW_DTYPE.itemsize == 72 and capi.VIEW_DTYPE.fields["out_offset"][1] == 32
+    assert capi.VIEW_DTYPE.fields["mount_q"][1] == 40 and capi.VIEW_DTYPE.fields["mount_t"][1] == 56
+    assert capi.VIEW_DTYPE.fields["swarm"][1] == 68
     assert capi.NODE_DTYPE.itemsize == 128 and capi.TRI_DTYPE.itemsize == 48
     assert capi.NODE_DTYPE.fields["child"][1] == 96 and capi.NODE_DTYPE.fields["count"][1] == 112
 

@@ -70,7 +70,7 @@ def _rounding_amplification(s0, acts, p):
     return float((np.abs(a - b) / np.maximum(1.0, np.abs(a))).max())
 
 
-@pytest.mark.parametrize("variant", ["ctbr_forest", "srt", "euler_nsub4", "hover"])
+@pytest.mark.parametrize("variant", ["ctbr_forest", "srt", "euler_nsub4", "hover", "ps", "lv", "ps_euler_nsub2"])
 def test_dynamics_batch_variants(vf, variant):
     """Local parity (oracle stepped from every GPU state) at 1e-5 for every variant; 100-step
     trajectories at 1e-5 for the CTBR/RK4 benchmark configuration, and for the other variants
@@ -80,11 +80,18 @@ def test_dynamics_batch_variants(vf, variant):
         p = default_params(ctrl=odyn.SRT)
     elif variant == "euler_nsub4":
         p = default_params(integrator=odyn.EULER, n_sub=4)
+    elif variant == "ps":
+        p = default_params(ctrl=odyn.PS)
+    elif variant == "ps_euler_nsub2":
+        p = default_params(ctrl=odyn.PS, integrator=odyn.EULER, n_sub=2)
+    elif variant == "lv":
+        p = default_params(ctrl=odyn.LV)
     else:
         p = default_params()
     forest = scenes.forest(seed=3, n_trees=300)
     n = 200
     s0 = agents.forest_starts(4, n, forest, p)
+    rng = np.random.default_rng(12)
     if variant == "srt":
         # single-rotor thrusts around hover (+-10 %); open loop, so the attitude random-walks
         rng = np.random.default_rng(9)
@@ -92,6 +99,14 @@ def test_dynamics_batch_variants(vf, variant):
         acts = (f_hover * rng.uniform(0.9, 1.1, size=(100, n, 4))).astype(np.float32)
     elif variant == "hover":
         acts = np.tile(np.array([p["g"], 0, 0, 0], dtype=np.float32), (100, n, 1))
+    elif variant.startswith("ps"):
+        # step commands: a goal within 3 m per axis and a yaw, held for 50 steps, then a second one
+        goal = np.concatenate([s0[:, 0:3] + rng.uniform(-3, 3, (n, 3)), rng.uniform(-np.pi, np.pi, (n, 1))], 1)
+        goal2 = np.concatenate([goal[:, 0:3] + rng.uniform(-3, 3, (n, 3)), rng.uniform(-np.pi, np.pi, (n, 1))], 1)
+        acts = np.concatenate([np.tile(goal, (50, 1, 1)), np.tile(goal2, (50, 1, 1))]).astype(np.float32)
+    elif variant == "lv":
+        cmd = np.concatenate([rng.uniform(-2, 2, (4, n, 3)), rng.uniform(-np.pi, np.pi, (4, n, 1))], 2)
+        acts = np.repeat(cmd, 25, axis=0).astype(np.float32)
     else:
         acts = agents.random_actions(5, 100, n, p)
     header(f"dynamics: {variant}, {n} agents x 100 steps")
@@ -101,7 +116,7 @@ def test_dynamics_batch_variants(vf, variant):
     ref = odyn.rollout(s0, acts, p)
     err = max(state_close(gpu[k], ref[k]) for k in range(101))
     tol = STATE_TOL
-    if variant in ("srt", "euler_nsub4"):
+    if variant != "ctbr_forest" and variant != "hover":
         tol = max(STATE_TOL, 32 * _rounding_amplification(s0, acts, p))
     assert err <= tol, f"{variant}: max state error {err:.3e} (bound {tol:.3e})"
     if variant == "hover":
@@ -385,6 +400,54 @@ def test_multi_scene_mixed_resolution(vf):
         compare_render(d[px], i[px], None, ref, 100.0, f"agent {a}")
     for s in sids:
         ctx.free_scene(s)
+
+
+def test_spatial_order_changes_nothing(vf):
+    """The (scene, position) render order of large batches moves work between workgroups only:
+    split steps and renders with and without it are bitwise equal, over two scenes, env slots,
+    mixed sizes and a batch just past the ordering threshold; every output pixel is written."""
+    sim, ctx = vf
+    p = default_params()
+    scs = [scenes.forest(seed=3, n_trees=300), scenes.box_room(seed=1)]
+    sids = [ctx.build_scene(s["verts"], s["tris"], s["rgb"]) for s in scs]
+    rng = np.random.default_rng(77)
+    n, n_slots = 300, 340
+    s0 = np.concatenate([agents.forest_starts(9, n_slots - 40, scs[0], p),
+                         agents.make_states(rng.uniform([1, 1, 1], [9, 9, 3], (40, 3)), p)])
+    env = rng.permutation(n_slots)[:n].astype(np.int32)
+    which = (env >= n_slots - 40).astype(np.int64)
+    hw = np.array([(64, 64), (40, 24)])[rng.integers(0, 2, n)]
+    views, npx, offs, mh, mw = sim.make_views(n, np.array(sids)[which], hw)
+    acts = _dev(agents.random_actions(3, 1, n, p)[0])
+    env_t = torch.as_tensor(env).cuda()
+    outs = []
+    header("spatial order on/off: 300 agents, 2 scenes")
+    for on in (True, False):
+        ctx.set_spatial_order(on)
+        ctx.set_launch_mode(False)
+        st = _dev(s0)
+        depth = torch.full((npx,), float("nan")).cuda()
+        ids = torch.full((npx,), -7, dtype=torch.int32).cuda()
+        rgb = torch.zeros(3 * npx, dtype=torch.uint8).cuda()
+        ctx.step(p, st, acts, views=views, env_idx=env_t, max_hw=(mh, mw), depth=depth, tri_id=ids, rgb=rgb,
+                 out_pixels=npx)
+        d2 = torch.full((npx,), float("nan")).cuda()
+        ctx.render(st, views, n=n, env_idx=env_t, max_hw=(mh, mw), depth=d2, out_pixels=npx)
+        ctx.sync_check()
+        outs.append([t.cpu().numpy() for t in (st, depth, ids, rgb, d2)])
+    ctx.set_spatial_order(True)
+    ctx.set_launch_mode(None)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b, equal_nan=False)
+    assert not np.isnan(outs[0][1]).any() and not (outs[0][2] == -7).any()
+    # spot-check a few agents against the oracle
+    for a in (0, 137, 299):
+        h, w = hw[a]
+        ref = oren.render_view(outs[0][0][env[a]].astype(np.float64), scs[which[a]], h, w, math.pi / 2)
+        px = slice(offs[a], offs[a] + h * w)
+        compare_render(outs[0][1][px], outs[0][2][px], None, ref, 100.0, f"agent {a}")
+    for sid in sids:
+        ctx.free_scene(sid)
 
 
 # ---------------------------------------------------------------------------

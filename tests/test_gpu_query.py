@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from oracle import render as oren
-from workloads import scenes
+from workloads import agents, scenes
 
 pytestmark = pytest.mark.gpu
 
@@ -87,5 +87,41 @@ def test_closest_point_per_point_scenes(vf):
         ref, _, _ = oren.closest_points(pts[i:i + 1].astype(np.float64), sc["verts"], sc["tris"])
         assert abs(d[i] - ref[0]) <= TOL * max(1.0, ref[0])
     # a point on the sphere's centre is at the inscribed radius from every face
+    ctx.free_scene(sa)
+    ctx.free_scene(sb)
+
+
+def test_collision_check_from_states(vf):
+    """Agent mode: positions come from state rows through env_idx, scenes from the views; the contact
+    flag is dist <= radius and rel points from the agent to its nearest obstacle point."""
+    sim, ctx = vf
+    from workloads import default_params
+    a, b = scenes.box_room(seed=1), scenes.forest(seed=3, n_trees=200)
+    sa = ctx.build_scene(a["verts"], a["tris"], a["rgb"])
+    sb = ctx.build_scene(b["verts"], b["tris"], b["rgb"])
+    rng = np.random.default_rng(8)
+    n_slots, n = 50, 40
+    pos = np.concatenate([rng.uniform([0.2, 0.2, 0.2], [9.8, 9.8, 3.8], (25, 3)),
+                          rng.uniform([-18, -18, 0.1], [18, 18, 5], (25, 3))])
+    states = agents.make_states(pos, default_params())
+    slot = rng.permutation(n_slots)[:n].astype(np.int32)
+    sids = np.where(slot < 25, sa, sb)
+    views, _, _, _, _ = sim.make_views(n, sids, (8, 8))
+    rel = torch.empty((n, 3)).cuda()
+    col = torch.empty(n, dtype=torch.uint8).cuda()
+    radius = 0.4
+    d = ctx.collision(torch.as_tensor(states).cuda(), views, radius, n=n,
+                      env_idx=torch.as_tensor(slot).cuda(), rel=rel, collided=col)
+    ctx.sync_check()
+    d, rel, col = d.cpu().numpy(), rel.cpu().numpy(), col.cpu().numpy()
+    for i in range(n):
+        sc = a if sids[i] == sa else b
+        p = states[slot[i], 0:3].astype(np.float64)
+        ref, pt, _ = oren.closest_points(p[None], sc["verts"], sc["tris"])
+        assert abs(d[i] - ref[0]) <= TOL * max(1.0, ref[0])
+        assert np.allclose(rel[i], pt[0] - p, atol=TOL * max(1.0, ref[0]) * 2)
+        if abs(ref[0] - radius) > 1e-4:
+            assert col[i] == (ref[0] <= radius)
+    assert col.sum() > 0 and col.sum() < n
     ctx.free_scene(sa)
     ctx.free_scene(sb)

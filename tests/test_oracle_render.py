@@ -299,3 +299,91 @@ def test_frustum_prefilter_never_changes_a_result():
                 b = ren.render_view(st, scene, hw[0], hw[1], fov, cull=False)
                 assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["depth"], b["depth"])
                 assert np.array_equal(a["mask"], b["mask"])
+
+
+def test_camera_mount_down_facing_with_offset():
+    """A level, yawed body with a camera mounted pitched 90 deg down and offset by t_m: the camera
+    sits at height z + t_m,z (a level body keeps body z vertical), so every planar depth is z + t_m,z;
+    the offset's horizontal part moves the camera without changing any depth."""
+    floor = scenes.floor_quad(half=100.0)
+    for z, yaw, tm in ((1.5, 0.0, (0.1, 0.0, -0.05)), (2.25, 1.1, (-0.3, 0.2, 0.125))):
+        st = _state([0.4, -0.7, z], yaw_quat([yaw])[0])
+        r = ren.render_view(st, floor, 24, 32, math.radians(90), mount=(_pitch_quat(math.pi / 2), tm))
+        assert np.all(r["id"] >= 0)
+        assert np.allclose(r["depth"], z + tm[2], rtol=1e-12, atol=0)
+
+
+def test_camera_mount_forward_offset_toward_a_wall():
+    """A forward camera offset by t_m = (a, b, c) in a body yawed by psi, facing the wall x = L of a
+    room: the centre ray leaves p + R_z(psi) t_m along (cos psi, sin psi, 0); at yaw 0 its depth is
+    L - p_x - a, and for a camera yawed back by -psi on a body yawed by psi the image is the one of an
+    unyawed body at the same camera position."""
+    room = scenes.box_interior(np.array([0.0, 0.0, 0.0]), np.array([10.0, 10.0, 4.0]), split=2)
+    st = _state([3.0, 5.0, 2.0], [1.0, 0.0, 0.0, 0.0])
+    r = ren.render_view(st, room, 2, 2, math.radians(20), mount=((1.0, 0.0, 0.0, 0.0), (0.25, 0.1, -0.2)))
+    # the four centre-adjacent pixels all hit the wall x = 10 with planar depth 10 - 3 - 0.25
+    assert np.allclose(r["depth"], 10.0 - 3.0 - 0.25, rtol=1e-12)
+    psi = 0.7
+    body = _state([3.0, 5.0, 2.0], yaw_quat([psi])[0])
+    tm = np.array([0.25, 0.1, -0.2])
+    mounted = ren.render_view(body, room, 16, 16, math.radians(90), mount=(yaw_quat([-psi])[0], tm))
+    c, s_ = math.cos(psi), math.sin(psi)
+    cam = np.array([3.0 + c * tm[0] - s_ * tm[1], 5.0 + s_ * tm[0] + c * tm[1], 2.0 + tm[2]])
+    plain = ren.render_view(_state(cam, [1.0, 0.0, 0.0, 0.0]), room, 16, 16, math.radians(90))
+    assert np.allclose(mounted["depth"], plain["depth"], rtol=1e-12)
+
+
+def test_box_entry_closed_form_and_orientation():
+    """A member box straight ahead at distance D: the centre rays enter its near face at D - h_x; turned
+    90 deg about z the near face is the one at h_y.  The entry point lies on the box surface and no
+    earlier sample along the ray is inside the box (brute-force march)."""
+    half = np.array([0.15, 0.1, 0.05])
+    o = np.zeros(3)
+    dirs = np.array([[1.0, 0.0, 0.0], [1.0, 0.01, 0.0], [1.0, -0.005, 0.004]])
+    for yaw, face in ((0.0, half[0]), (math.pi / 2, half[1])):
+        b = ren.cast_boxes(o, dirs, np.array([[4.0, 0.0, 0.0]]), np.array([yaw_quat([yaw])[0]]), half)
+        assert np.all(b["k"] == 0)
+        assert np.allclose(b["t"], 4.0 - face, rtol=1e-12)
+    rng = np.random.default_rng(2)
+    centers = rng.uniform(-3, 3, (4, 3))
+    quats = rng.normal(size=(4, 4))
+    quats /= np.linalg.norm(quats, axis=1, keepdims=True)
+    half = np.array([0.8, 0.6, 0.5])
+    d = np.concatenate([rng.normal(size=(200, 3)), centers[rng.integers(0, 4, 200)] + rng.normal(0, 0.5, (200, 3))])
+    b = ren.cast_boxes(o, d, centers, quats, half, near=0.01, far=100.0)
+    assert (b["k"] >= 0).sum() > 0
+    for i in np.nonzero(b["k"] >= 0)[0]:
+        k = b["k"][i]
+        rot = ren.quat_to_rot(quats[k])
+        x = (o + b["t"][i] * d[i] - centers[k]) @ rot
+        assert abs(np.max(np.abs(x) / half) - 1.0) < 1e-9
+    # brute force: march every ray and find the first sample inside any box
+    ts = np.linspace(0.01, 10.0, 40001)
+    for i in range(0, 400, 7):
+        pts = o + ts[:, None] * d[i]
+        inside = np.zeros(ts.shape, dtype=bool)
+        for k in range(4):
+            x = (pts - centers[k]) @ ren.quat_to_rot(quats[k])
+            inside |= np.all(np.abs(x) <= half, axis=1)
+        if inside.any():
+            first = ts[np.argmax(inside)]
+            assert b["k"][i] >= 0 and first - 5e-4 <= b["t"][i] <= first
+        elif b["k"][i] >= 0:
+            assert b["t"][i] > 10.0 or b["edge"][i] < 1e-3 or b["gap"][i] < 1e-3
+
+
+def test_swarm_members_occlude_and_tie_to_the_mesh():
+    """A member between the camera and a wall takes the pixel (its id and colour); a member behind the
+    wall is hidden; a camera inside a member's box does not see that box."""
+    wall = scenes.plane_quad((6.0, -5.0, -5.0), (0.0, 10.0, 0.0), (0.0, 0.0, 10.0))
+    st = _state([0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0])
+    half = (0.15, 0.15, 0.05)
+    others = {"centers": np.array([[3.0, 0.0, 0.0], [8.0, 0.0, 0.0], [0.0, 0.0, 0.0]]),
+              "quats": np.array([[1.0, 0, 0, 0]] * 3), "half": half, "rgb": (10, 20, 30), "ids": [100, 101, 102]}
+    r = ren.render_view(st, wall, 9, 9, math.radians(10), others=others)
+    c = r["depth"][4, 4]
+    assert r["id"][4, 4] == 100 and abs(c - (3.0 - 0.15)) < 1e-12
+    assert tuple(r["rgb"][:, 4, 4]) == (10, 20, 30)
+    # corner pixels pass beside the member and hit the wall at its planar distance
+    assert r["id"][0, 0] in (0, 1) and abs(r["depth"][0, 0] - 6.0) < 1e-12
+    assert not np.any(r["id"] == 101) and not np.any(r["id"] == 102)

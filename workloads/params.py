@@ -7,6 +7,9 @@ The airframe numbers (mass 1.0 kg, arm 0.15 m, inertia diag(0.0025, 0.0025,
 yaw reaction ratio 0.016 m, per-rotor thrust limit 0.75 m g (thrust-to-weight 3),
 body-rate gains diag(20, 20, 10) 1/s, gravity 9.81 m/s^2 along -z, no quadratic
 drag term, one sub-step per control step, RK4 integration, CTBR control.
+The position / velocity controllers (PS, LV) use position gains 4 1/s^2,
+velocity gains 4 1/s, attitude gains (8, 8, 4) 1/s and a 45 degree tilt limit
+(readings: the paper names the controllers but gives no law or gains).
 
 Values are plain Python floats; callers cast them to float32 for the device.
 """
@@ -16,12 +19,15 @@ PARAM_FIELDS = (
     "dt", "n_sub", "integrator", "ctrl",
     "mass", "arm", "J", "tau_motor", "kappa_yaw", "f_max",
     "k_lin", "c_quad", "g", "k_rate",
+    "k_pos", "k_vel", "k_att", "max_tilt",
 )
 
 INTEGRATOR_RK4 = 0
 INTEGRATOR_EULER = 1
 CTRL_CTBR = 0
 CTRL_SRT = 1
+CTRL_PS = 2
+CTRL_LV = 3
 
 
 def default_params(**overrides):
@@ -43,6 +49,10 @@ def default_params(**overrides):
         "c_quad": (0.0, 0.0, 0.0),
         "g": g,
         "k_rate": (20.0, 20.0, 10.0),
+        "k_pos": (4.0, 4.0, 4.0),
+        "k_vel": (4.0, 4.0, 4.0),
+        "k_att": (8.0, 8.0, 4.0),
+        "max_tilt": 0.7853981633974483,
     }
     for k, v in overrides.items():
         if k not in p:
