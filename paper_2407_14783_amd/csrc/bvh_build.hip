@@ -269,6 +269,55 @@ __global__ void k_radix_tree(const uint32_t* __restrict__ k, int32_t n, int32_t*
     last[i] = hi;
 }
 
+// Parent links of the binary radix tree (-1 above the root).
+__global__ void k_parents(const int32_t* __restrict__ left, const int32_t* __restrict__ right, int32_t n,
+                          int32_t* __restrict__ par_int, int32_t* __restrict__ par_leaf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    if (i == 0) par_int[0] = -1;
+    int32_t l = left[i], r = right[i];
+    if (l >= 0) par_int[l] = i; else par_leaf[-l - 1] = i;
+    if (r >= 0) par_int[r] = i; else par_leaf[-r - 1] = i;
+}
+
+// Boxes of the binary tree's inner nodes, bottom-up: one thread per leaf climbs while it is the
+// second of the two children to arrive at a node (an atomic counter per node), so every node is
+// written once, after both children.  Unions of min/max are exact: the result does not depend on
+// the arrival order.
+__global__ void k_binary_bounds(const int32_t* __restrict__ left, const int32_t* __restrict__ right, int32_t n,
+                                const uint32_t* __restrict__ sorted_vals, const float4* __restrict__ tlo,
+                                const float4* __restrict__ thi, const int32_t* __restrict__ par_int,
+                                const int32_t* __restrict__ par_leaf, uint32_t* __restrict__ flags, float4* nlo,
+                                float4* nhi) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int32_t p = par_leaf[j];
+    while (p >= 0) {
+        __threadfence();
+        if (atomicAdd(&flags[p], 1u) == 0u) return;
+        __threadfence();
+        float l[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, h[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+        for (int side = 0; side < 2; ++side) {
+            int32_t c = side == 0 ? left[p] : right[p];
+            float a[3], b[3];
+            if (c >= 0) {
+                const volatile float* vl = (const volatile float*)(nlo + c);
+                const volatile float* vh = (const volatile float*)(nhi + c);
+                for (int k = 0; k < 3; ++k) { a[k] = vl[k]; b[k] = vh[k]; }
+            } else {
+                uint32_t t = sorted_vals[-c - 1];
+                float4 x = tlo[t], y = thi[t];
+                a[0] = x.x; a[1] = x.y; a[2] = x.z;
+                b[0] = y.x; b[1] = y.y; b[2] = y.z;
+            }
+            for (int k = 0; k < 3; ++k) { l[k] = fminf(l[k], a[k]); h[k] = fmaxf(h[k], b[k]); }
+        }
+        nlo[p] = make_float4(l[0], l[1], l[2], 0.f);
+        nhi[p] = make_float4(h[0], h[1], h[2], 0.f);
+        p = par_int[p];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // collapse to 4-wide nodes, one level per launch
 // ---------------------------------------------------------------------------
@@ -277,8 +326,15 @@ struct TreeView {
     const int32_t* right;
     const int32_t* first;
     const int32_t* last;
+    const float4* nlo;   // inner-node boxes
+    const float4* nhi;
     __device__ int count(int32_t r) const { return r >= 0 ? last[r] - first[r] + 1 : 1; }
     __device__ int start(int32_t r) const { return r >= 0 ? first[r] : -r - 1; }
+    __device__ float area(int32_t r) const {
+        float4 a = nlo[r], b = nhi[r];
+        float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+        return dx * dy + dy * dz + dz * dx;
+    }
 };
 
 constexpr int32_t kEmpty = INT32_MIN;
@@ -296,12 +352,15 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
         c[0] = tv.left[r];
         c[1] = tv.right[r];
         nk = 2;
+        // open the child with the largest surface area among those too big for a leaf, until there
+        // are four (the greedy collapse of a binary tree into a wide one)
         while (nk < 4) {
-            int best = -1, bestc = kLeafMax;
+            int best = -1;
+            float besta = -1.0f;
             for (int k = 0; k < nk; ++k) {
-                if (c[k] >= 0) {
-                    int cc = tv.count(c[k]);
-                    if (cc > bestc) { bestc = cc; best = k; }
+                if (c[k] >= 0 && tv.count(c[k]) > kLeafMax) {
+                    float ar = tv.area(c[k]);
+                    if (ar > besta) { besta = ar; best = k; }
                 }
             }
             if (best < 0) break;
@@ -498,6 +557,10 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     GET(hist, 256 * (int64_t)nb_sort); GET(offs, 256 * (int64_t)nb_sort); GET(total, 4);
     GET(left, nt); GET(right, nt); GET(first, nt); GET(last, nt);
     GET(entries, nt + 1); GET(kids, 4 * (int64_t)(nt + 1)); GET(n_inner, nt + 1); GET(prefix, nt + 1);
+    int32_t *par_int, *par_leaf;
+    uint32_t* flags;
+    float4 *nlo, *nhi;
+    GET(par_int, nt); GET(par_leaf, nt); GET(flags, nt); GET(nlo, nt); GET(nhi, nt);
 #undef GET
 
     hipEvent_t ev0, ev1;
@@ -546,7 +609,12 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     } else {
         hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, ka, nt, left, right, first,
                            last);
-        TreeView tv{left, right, first, last};
+        hipLaunchKernelGGL(k_parents, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, left, right, nt, par_int,
+                           par_leaf);
+        VF_HIP(hipMemsetAsync(flags, 0, (size_t)nt * 4, st));
+        hipLaunchKernelGGL(k_binary_bounds, dim3(blocks_for(nt, 256)), dim3(256), 0, st, left, right, nt, vals, tlo,
+                           thi, par_int, par_leaf, flags, nlo, nhi);
+        TreeView tv{left, right, first, last, nlo, nhi};
         int32_t root = 0;
         VF_HIP(hipMemcpyAsync(entries, &root, sizeof(int32_t), hipMemcpyHostToDevice, st));
         int32_t base = 0, n_level = 1;
@@ -628,6 +696,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     out->desc.sorted_of = sorted_of;
     out->desc.n_tris = nt;
     out->desc.root_leaf = single_leaf ? 1 : 0;
+    out->desc.n_nodes = (int32_t)n_nodes;
     out->desc.valid = 1;
     return VF_OK;
 }

@@ -149,6 +149,10 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             uint32_t tw[12 * kLeafMax];
 #pragma unroll
             for (int i = 0; i < 12 * kLeafMax; ++i) tw[i] = tp[i];
+            // the padding words are never used; naming them keeps the leaf one run of 16-dword loads
+            // instead of many small ones
+#pragma unroll
+            for (int j = 0; j < kLeafMax; ++j) asm volatile("" ::"s"(tw[12 * j + 7]), "s"(tw[12 * j + 11]));
             if (STATS) {
                 ts.tri_wave += cnt;
                 ts.tri_lane += cnt * n_valid;
@@ -290,10 +294,13 @@ k_render(RenderArgs a) {
     } else {
         if (threadIdx.x < 17) pose[threadIdx.x] = a.state[slot * 17 + threadIdx.x];
     }
-    vf_view vw = a.views[agent];
+    // the view and scene records stay in vector registers: the traversal needs the scalar ones
+    const vf_view vw = a.views[agent];
     if (threadIdx.x == 0) ok_shared = view_ok(a, vw) ? 1 : 0;
     __syncthreads();
     if (!ok_shared) return;
+    const SceneDesc sc = a.scenes[vw.scene_id];
+
 
     // the wavefront's packet: kPacketRows x kPacketCols 8x8 sub-tiles, one ray of each per lane
     constexpr int NR = kPacketRows * kPacketCols;
@@ -318,7 +325,6 @@ k_render(RenderArgs a) {
     const float tan_h = tanf(0.5f * vw.hfov);
 #pragma unroll
     for (int k = 0; k < NR; ++k) pixel_ray(rot, tan_h, vw.H, vw.W, row[k], col[k], d[k]);
-    const SceneDesc sc = a.scenes[vw.scene_id];
     float t_best[NR];
     int32_t id_best[NR];
     TraceStats ts = {0, 0, 0, 0, 0, 0};

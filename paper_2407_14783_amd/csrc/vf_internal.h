@@ -77,7 +77,8 @@ struct alignas(16) SceneDesc {
     int32_t n_tris;
     int32_t root_leaf;        // 1: the whole scene is one leaf (T <= kLeafMax), no nodes
     int32_t valid;
-    int32_t pad[5];
+    int32_t n_nodes;
+    int32_t pad[4];
 };
 static_assert(sizeof(SceneDesc) == 64, "scene table entry is 64 bytes");
 static_assert(sizeof(vf_view) == 72, "view descriptor is 72 bytes");
