@@ -63,19 +63,25 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                                              TraceStats& ts) {
     const Node4 CONST_AS* nodes = (const Node4 CONST_AS*)sc.nodes;
     const Tri CONST_AS* tris = (const Tri CONST_AS*)sc.tris;
-    float inv[NR][3];
+    float inv[NR][3], oi[NR][3];
     int n_valid = 0;
     bool any = false;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        for (int k = 0; k < 3; ++k) inv[r][k] = safe_inv(d[r][k]);
+        for (int k = 0; k < 3; ++k) {
+            inv[r][k] = safe_inv(d[r][k]);
+            oi[r][k] = -o[k] * inv[r][k];
+        }
         t_best[r] = t_far;
         id_best[r] = -1;
         any = any || valid[r];
         n_valid += valid[r] ? 1 : 0;
     }
-    // 1 + 2 gamma_3 (Ize 2013) keeps the slab test conservative in float32
-    const float grow = 1.0000004f;
+    // 1 + 2 gamma_3 (Ize 2013) widens the slab exit.  The fused form lo * (1/d) - o * (1/d) adds an
+    // error of about |o| 2^-24 in space; the child boxes' padding of 2^-19 (|x| + 1) plus the entry
+    // shrunk by the same relative margin (distance x 4e-7) always exceed it, so no box a ray meets
+    // is rejected.
+    const float grow = 1.0000004f, shrink = 0.9999996f;
     int oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
     oct = uniform_i(oct);
     if (__ballot(any) == 0ull) return;
@@ -107,10 +113,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 bool h = false;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
-                    float tx0 = (lox - o[0]) * inv[r][0], tx1 = (hix - o[0]) * inv[r][0];
-                    float ty0 = (loy - o[1]) * inv[r][1], ty1 = (hiy - o[1]) * inv[r][1];
-                    float tz0 = (loz - o[2]) * inv[r][2], tz1 = (hiz - o[2]) * inv[r][2];
-                    float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near));
+                    // (lo - o) / d as one fused multiply-add: lo * (1/d) - o * (1/d)
+                    float tx0 = fmaf(lox, inv[r][0], oi[r][0]), tx1 = fmaf(hix, inv[r][0], oi[r][0]);
+                    float ty0 = fmaf(loy, inv[r][1], oi[r][1]), ty1 = fmaf(hiy, inv[r][1], oi[r][1]);
+                    float tz0 = fmaf(loz, inv[r][2], oi[r][2]), tz1 = fmaf(hiz, inv[r][2], oi[r][2]);
+                    float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near)) * shrink;
                     float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
                     h = h | (valid[r] & (t0 <= fminf(t1, t_best[r])));
                 }
