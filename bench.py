@@ -228,8 +228,8 @@ def bptt_throughput(ctx, sim, params, n=1024, horizon=64, k=8):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(agents shard by scene with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path here "
+              "(agents would shard by scene with no exchange)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
