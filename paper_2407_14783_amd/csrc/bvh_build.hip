@@ -396,7 +396,8 @@ __global__ void k_collapse_emit(TreeView tv, int32_t* __restrict__ entries, int3
             nd.count[k] = 0;
             ++at;
         } else {
-            nd.child[k] = -(tv.start(c) + 1);
+            // a leaf's slot holds the traversal's stack entry: -((first << 3 | (count - 1)) + 1)
+            nd.child[k] = -(((tv.start(c) << 3) | (tv.count(c) - 1)) + 1);
             nd.count[k] = (uint8_t)tv.count(c);
         }
     }
@@ -428,7 +429,7 @@ __global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t 
                 l[2] = fminf(l[2], ch.lo_z[j]); h[2] = fmaxf(h[2], ch.hi_z[j]);
             }
         } else if (cnt > 0) {
-            int f = -c - 1;
+            int f = (-c - 1) >> 3;
             for (int j = 0; j < cnt; ++j) {
                 uint32_t t = sorted_vals[f + j];
                 float4 a = tlo[t], b = thi[t];
@@ -480,7 +481,7 @@ __global__ void k_single_leaf_root(Node4* __restrict__ nodes, int32_t nt, const 
         nd.lo_x[k] = v ? pad_down(l[0]) : FLT_MAX; nd.hi_x[k] = v ? pad_up(h[0]) : -FLT_MAX;
         nd.lo_y[k] = v ? pad_down(l[1]) : FLT_MAX; nd.hi_y[k] = v ? pad_up(h[1]) : -FLT_MAX;
         nd.lo_z[k] = v ? pad_down(l[2]) : FLT_MAX; nd.hi_z[k] = v ? pad_up(h[2]) : -FLT_MAX;
-        nd.child[k] = v ? -1 : -1;
+        nd.child[k] = v ? -(((0 << 3) | (nt - 1)) + 1) : -1;
         nd.count[k] = v ? (uint8_t)nt : 0;
     }
     nd.order_lo = 0xE4E4E4E4u;  // identity order 0,1,2,3 for every octant

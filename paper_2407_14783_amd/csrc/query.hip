@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(128) k_closest_point(QueryArgs q) {
                 float d2 = box_dist2(p[0], p[1], p[2], nd.lo_x[k], nd.hi_x[k], nd.lo_y[k], nd.hi_y[k], nd.lo_z[k],
                                      nd.hi_z[k]);
                 if (d2 > best) continue;
-                int32_t en = c >= 0 ? c : -((((-c - 1) << 3) | (cnt - 1)) + 1);
+                const int32_t en = c;   // node index, or the leaf's encoded range
                 // insertion into the small list, farthest first
                 int j = nk++;
                 while (j > 0 && dk[j - 1] < d2) {

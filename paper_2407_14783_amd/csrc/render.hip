@@ -131,15 +131,12 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 int k = (byte >> (2 * i)) & 3;
                 uint64_t hm = k == 0 ? hitmask[0] : k == 1 ? hitmask[1] : k == 2 ? hitmask[2] : hitmask[3];
                 if (hm != 0ull) {
-                    int32_t c = (int32_t)(k == 0 ? w[24] : k == 1 ? w[25] : k == 2 ? w[26] : w[27]);
-                    int32_t cnt = (int32_t)((counts >> (8 * k)) & 255u);
-                    int32_t e = c >= 0 ? c : -((((-c - 1) << 3) | (cnt - 1)) + 1);
+                    // the slot word is the stack entry: a node index, or the leaf's encoded range
+                    const int32_t e = (int32_t)(k == 0 ? w[24] : k == 1 ? w[25] : k == 2 ? w[26] : w[27]);
                     if (sp < kStackCap) {
-                        // write lane sp of the two stack registers (a lane compare + select)
-                        if (sp < 64)
-                            stk0 = lane_id() == sp ? e : stk0;
-                        else
-                            stk1 = lane_id() == sp - 64 ? e : stk1;
+                        // write lane sp of the two stack registers (lane compares + selects, no branch)
+                        stk0 = lane_id() == sp ? e : stk0;
+                        stk1 = lane_id() == sp - 64 ? e : stk1;
                         ++sp;
                     } else {
                         overflow = true;
@@ -198,7 +195,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
         }
         if (sp == 0) break;
         --sp;
-        entry = sp < 64 ? __builtin_amdgcn_readlane(stk0, sp) : __builtin_amdgcn_readlane(stk1, sp - 64);
+        {
+            const int32_t a0 = __builtin_amdgcn_readlane(stk0, sp & 63);
+            const int32_t a1 = __builtin_amdgcn_readlane(stk1, sp & 63);
+            entry = sp < 64 ? a0 : a1;
+        }
     }
     if (overflow && lane_id() == 0) atomicOr(err, kErrStack);
     if (STATS)

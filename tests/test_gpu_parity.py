@@ -478,7 +478,8 @@ def test_bvh_invariants_and_deterministic_rebuild(vf):
                 valid = (nodes["child"][c] >= 0) | (nodes["count"][c] > 0)
                 assert np.all(lo[c][valid] >= lo[ni, k]) and np.all(hi[c][valid] <= hi[ni, k])
             elif cnt > 0:
-                f = -c - 1
+                f = (-c - 1) >> 3
+                assert ((-c - 1) & 7) + 1 == cnt
                 covered[f:f + cnt] += 1
                 ids = tris["id"][f:f + cnt]
                 tv = v[t[ids]].reshape(-1, 3)
