@@ -186,8 +186,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float u = (sx * px + sy * py + sz * pz) * inv_det;
                     float v = (dr[0] * qx + dr[1] * qy + dr[2] * qz) * inv_det;
                     float t = tq * inv_det;
-                    bool h = valid[r] && det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t >= t_near;
-                    bool take = h && (t < t_best[r] || (t == t_best[r] && (id_best[r] < 0 || id < id_best[r])));
+                    // bitwise, not short-circuit: no divergent branches.  An empty best (id -1) compares
+                    // as the largest unsigned id, so any hit at the same depth replaces it.
+                    const bool h = valid[r] & (det != 0.0f) & (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) &
+                                   (t >= t_near);
+                    const bool take = h & ((t < t_best[r]) | ((t == t_best[r]) & ((uint32_t)id < (uint32_t)id_best[r])));
                     t_best[r] = take ? t : t_best[r];
                     id_best[r] = take ? id : id_best[r];
                 }
