@@ -133,7 +133,7 @@ typedef struct vf_scene_info {
  * child[k] >= 0: index of an inner node; child[k] < 0 with count[k] > 0: leaf
  * of count[k] triangles starting at sorted position first, encoded as
  * -child[k] - 1 = (first << 3) | (count[k] - 1); count[k] == 0 with
- * child[k] < 0 marks an empty slot.  order_lo/order_hi hold, for each of
+ * child[k] < 0 marks an empty slot, whose box is [FLT_MAX, FLT_MAX]^3.  order_lo/order_hi hold, for each of
  * the 8 ray-direction octants o (bit 0: x<0, bit 1: y<0, bit 2: z<0), a byte of
  * four 2-bit child slots in near-to-far order (octant o at bits 8*o..8*o+7 of
  * the 64-bit value order_hi:order_lo). */

@@ -441,6 +441,9 @@ __global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t 
         for (int a = 0; a < 3; ++a) { lo[k][a] = l[a]; hi[k][a] = h[a]; }
     }
     for (int k = 0; k < 4; ++k) {
+        // an empty slot gets the box [FLT_MAX, FLT_MAX]^3, which no ray enters
+        if (!valid[k])
+            for (int a = 0; a < 3; ++a) lo[k][a] = hi[k][a] = FLT_MAX;
         nd.lo_x[k] = lo[k][0]; nd.hi_x[k] = hi[k][0];
         nd.lo_y[k] = lo[k][1]; nd.hi_y[k] = hi[k][1];
         nd.lo_z[k] = lo[k][2]; nd.hi_z[k] = hi[k][2];
@@ -478,9 +481,9 @@ __global__ void k_single_leaf_root(Node4* __restrict__ nodes, int32_t nt, const 
     }
     for (int k = 0; k < 4; ++k) {
         bool v = k == 0;
-        nd.lo_x[k] = v ? pad_down(l[0]) : FLT_MAX; nd.hi_x[k] = v ? pad_up(h[0]) : -FLT_MAX;
-        nd.lo_y[k] = v ? pad_down(l[1]) : FLT_MAX; nd.hi_y[k] = v ? pad_up(h[1]) : -FLT_MAX;
-        nd.lo_z[k] = v ? pad_down(l[2]) : FLT_MAX; nd.hi_z[k] = v ? pad_up(h[2]) : -FLT_MAX;
+        nd.lo_x[k] = v ? pad_down(l[0]) : FLT_MAX; nd.hi_x[k] = v ? pad_up(h[0]) : FLT_MAX;
+        nd.lo_y[k] = v ? pad_down(l[1]) : FLT_MAX; nd.hi_y[k] = v ? pad_up(h[1]) : FLT_MAX;
+        nd.lo_z[k] = v ? pad_down(l[2]) : FLT_MAX; nd.hi_z[k] = v ? pad_up(h[2]) : FLT_MAX;
         nd.child[k] = v ? -(((0 << 3) | (nt - 1)) + 1) : -1;
         nd.count[k] = v ? (uint8_t)nt : 0;
     }

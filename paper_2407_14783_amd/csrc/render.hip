@@ -102,14 +102,13 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 ts.node_lane += n_valid;
                 ts.box_lane += 4 * n_valid;
             }
-            const uint32_t counts = w[28];
-            uint64_t hitmask[4];
+            // bit k: some ray of the packet enters child k's box (empty slots hold a box no ray enters)
+            uint32_t hb = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const float lox = __uint_as_float(w[k]), hix = __uint_as_float(w[4 + k]);
                 const float loy = __uint_as_float(w[8 + k]), hiy = __uint_as_float(w[12 + k]);
                 const float loz = __uint_as_float(w[16 + k]), hiz = __uint_as_float(w[20 + k]);
-                const bool slot = (int32_t)w[24 + k] >= 0 || ((counts >> (8 * k)) & 255u) != 0u;
                 bool h = false;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -121,16 +120,15 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
                     h = h | (valid[r] & (t0 <= fminf(t1, t_best[r])));
                 }
-                hitmask[k] = __ballot(h & slot);
+                hb |= (__ballot(h) != 0ull ? 1u : 0u) << k;
             }
             const uint64_t ord = ((uint64_t)w[30] << 32) | w[29];
             const uint32_t byte = (uint32_t)(ord >> (8 * oct)) & 255u;
             // push hit children far-to-near so the nearest is on top
 #pragma unroll
             for (int i = 3; i >= 0; --i) {
-                int k = (byte >> (2 * i)) & 3;
-                uint64_t hm = k == 0 ? hitmask[0] : k == 1 ? hitmask[1] : k == 2 ? hitmask[2] : hitmask[3];
-                if (hm != 0ull) {
+                const uint32_t k = (byte >> (2 * i)) & 3u;
+                if ((hb >> k) & 1u) {
                     // the slot word is the stack entry: a node index, or the leaf's encoded range
                     const int32_t e = (int32_t)(k == 0 ? w[24] : k == 1 ? w[25] : k == 2 ? w[26] : w[27]);
                     if (sp < kStackCap) {
