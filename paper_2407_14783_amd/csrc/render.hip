@@ -72,7 +72,8 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             inv[r][k] = safe_inv(d[r][k]);
             oi[r][k] = -o[k] * inv[r][k];
         }
-        t_best[r] = t_far;
+        // a lane outside the image gets a best depth of -1: no box or triangle test passes for it
+        t_best[r] = valid[r] ? t_far : -1.0f;
         id_best[r] = -1;
         any = any || valid[r];
         n_valid += valid[r] ? 1 : 0;
@@ -89,7 +90,6 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
     int stk0 = 0, stk1 = 0;
     int sp = 0;
     int32_t entry = 0;          // root: inner node 0
-    bool overflow = false;
     while (true) {
         if (entry >= 0) {
             // the whole 128-byte node in one burst of wave-uniform (scalar) loads
@@ -118,7 +118,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float tz0 = fmaf(loz, inv[r][2], oi[r][2]), tz1 = fmaf(hiz, inv[r][2], oi[r][2]);
                     float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near)) * shrink;
                     float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
-                    h = h | (valid[r] & (t0 <= fminf(t1, t_best[r])));
+                    h = h | (t0 <= fminf(t1, t_best[r]));
                 }
                 hb |= (__ballot(h) != 0ull ? 1u : 0u) << k;
             }
@@ -131,14 +131,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 if ((hb >> k) & 1u) {
                     // the slot word is the stack entry: a node index, or the leaf's encoded range
                     const int32_t e = (int32_t)(k == 0 ? w[24] : k == 1 ? w[25] : k == 2 ? w[26] : w[27]);
-                    if (sp < kStackCap) {
-                        // write lane sp of the two stack registers (lane compares + selects, no branch)
-                        stk0 = lane_id() == sp ? e : stk0;
-                        stk1 = lane_id() == sp - 64 ? e : stk1;
-                        ++sp;
-                    } else {
-                        overflow = true;
-                    }
+                    // write lane sp of the two stack registers (lane compares + selects, no branch);
+                    // the depth limit of the build bounds sp below kStackCap
+                    stk0 = lane_id() == sp ? e : stk0;
+                    stk1 = lane_id() == sp - 64 ? e : stk1;
+                    ++sp;
                 }
             }
         } else {
@@ -186,8 +183,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float t = tq * inv_det;
                     // bitwise, not short-circuit: no divergent branches.  An empty best (id -1) compares
                     // as the largest unsigned id, so any hit at the same depth replaces it.
-                    const bool h = valid[r] & (det != 0.0f) & (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) &
-                                   (t >= t_near);
+                    const bool h = (det != 0.0f) & (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t >= t_near);
                     const bool take = h & ((t < t_best[r]) | ((t == t_best[r]) & ((uint32_t)id < (uint32_t)id_best[r])));
                     t_best[r] = take ? t : t_best[r];
                     id_best[r] = take ? id : id_best[r];
@@ -202,7 +198,6 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             entry = sp < 64 ? a0 : a1;
         }
     }
-    if (overflow && lane_id() == 0) atomicOr(err, kErrStack);
     if (STATS)
         for (int r = 0; r < NR; ++r) ts.hits += (valid[r] && id_best[r] >= 0) ? 1 : 0;
 }

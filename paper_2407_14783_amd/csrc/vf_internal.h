@@ -33,6 +33,8 @@ constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 constexpr int kLeafMax = VF_LEAF_MAX;  // triangles per BVH leaf (at most 8: the stack entry keeps 3 bits)
 constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
 constexpr int kMaxBvhDepth = 40;      // builds deeper than this are rejected (3 pushes per level)
+// a packet keeps at most 3 pending siblings per level of its path plus the 4 children just pushed
+static_assert(3 * (kMaxBvhDepth - 1) + 4 <= kStackCap, "traversal stack cannot overflow");
 constexpr int kMaxScenes = 1024;
 constexpr int kMaxImage = 1024;
 
