@@ -97,6 +97,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             uint32_t w[32];
 #pragma unroll
             for (int i = 0; i < 32; ++i) w[i] = np[i];
+            asm volatile("" ::"s"(w[28]), "s"(w[31]));   // unused words: keeps two 16-dword loads
             if (STATS) {
                 ts.node_wave += 1;
                 ts.node_lane += n_valid;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 const float lox = __uint_as_float(w[k]), hix = __uint_as_float(w[4 + k]);
                 const float loy = __uint_as_float(w[8 + k]), hiy = __uint_as_float(w[12 + k]);
                 const float loz = __uint_as_float(w[16 + k]), hiz = __uint_as_float(w[20 + k]);
-                bool h = false;
+                uint64_t m = 0;   // lanes with a ray entering the box (the union over the lane's rays)
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     // (lo - o) / d as one fused multiply-add: lo * (1/d) - o * (1/d)
@@ -118,9 +119,9 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float tz0 = fmaf(loz, inv[r][2], oi[r][2]), tz1 = fmaf(hiz, inv[r][2], oi[r][2]);
                     float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near)) * shrink;
                     float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
-                    h = h | (t0 <= fminf(t1, t_best[r]));
+                    m |= __ballot(t0 <= fminf(t1, t_best[r]));
                 }
-                hb |= (__ballot(h) != 0ull ? 1u : 0u) << k;
+                hb |= (m != 0ull ? 1u : 0u) << k;
             }
             const uint64_t ord = ((uint64_t)w[30] << 32) | w[29];
             const uint32_t byte = (uint32_t)(ord >> (8 * oct)) & 255u;
@@ -130,7 +131,9 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 const uint32_t k = (byte >> (2 * i)) & 3u;
                 if ((hb >> k) & 1u) {
                     // the slot word is the stack entry: a node index, or the leaf's encoded range
-                    const int32_t e = (int32_t)(k == 0 ? w[24] : k == 1 ? w[25] : k == 2 ? w[26] : w[27]);
+                    const int32_t e01 = (int32_t)((k & 1u) ? w[25] : w[24]);
+                    const int32_t e23 = (int32_t)((k & 1u) ? w[27] : w[26]);
+                    const int32_t e = (k & 2u) ? e23 : e01;
                     // write lane sp of the two stack registers (lane compares + selects, no branch);
                     // the depth limit of the build bounds sp below kStackCap
                     stk0 = lane_id() == sp ? e : stk0;
