@@ -81,8 +81,12 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
     // 1 + 2 gamma_3 (Ize 2013) widens the slab exit.  The fused form lo * (1/d) - o * (1/d) adds an
     // error of about |o| 2^-24 in space; the child boxes' padding of 2^-19 (|x| + 1) plus the entry
     // shrunk by the same relative margin (distance x 4e-7) always exceed it, so no box a ray meets
-    // is rejected.
-    const float grow = 1.0000004f, shrink = 0.9999996f;
+    // is rejected.  The shrink is applied to the other side of the comparison: to the exit growth
+    // and to a copy of the best depth refreshed after every leaf.
+    const float grow2 = 1.000001f, unshrink = 1.0000005f;   // >= grow / shrink and 1 / shrink
+    float tb_box[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tb_box[r] = t_best[r] * unshrink;
     int oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
     oct = uniform_i(oct);
     if (__ballot(any) == 0ull) return;
@@ -117,9 +121,10 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float tx0 = fmaf(lox, inv[r][0], oi[r][0]), tx1 = fmaf(hix, inv[r][0], oi[r][0]);
                     float ty0 = fmaf(loy, inv[r][1], oi[r][1]), ty1 = fmaf(hiy, inv[r][1], oi[r][1]);
                     float tz0 = fmaf(loz, inv[r][2], oi[r][2]), tz1 = fmaf(hiz, inv[r][2], oi[r][2]);
-                    float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near)) * shrink;
-                    float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow;
-                    m |= __ballot(t0 <= fminf(t1, t_best[r]));
+                    // entry * shrink <= min(exit * grow, best)  <=>  entry <= min(exit * grow / shrink, best / shrink)
+                    float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_near));
+                    float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * grow2;
+                    m |= __ballot(t0 <= fminf(t1, tb_box[r]));
                 }
                 hb |= (m != 0ull ? 1u : 0u) << k;
             }
@@ -192,6 +197,8 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     id_best[r] = take ? id : id_best[r];
                 }
             }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) tb_box[r] = t_best[r] * unshrink;
         }
         if (sp == 0) break;
         --sp;
