@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 latency"
 # VALU lane-operations per test as issued by the traversal kernel:
 OPS_PER_BOX = 18       # 6 fused slab distances, 10 min/max, 1 mul (exit growth), 1 compare
-OPS_PER_TRI = 55       # Moller-Trumbore: 2 cross products, 3 dots, 3 subs, rcp, 3 muls, compares, selects
+OPS_PER_TRI = 42       # Moller-Trumbore: 2 cross products, 4 dots, 3 subs, rcp, 3 muls, 1 add, 8 compares, 2 selects
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
 HBM_PEAK_GBPS = 8000.0
 

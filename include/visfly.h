@@ -303,7 +303,7 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
                         const float half_extent[3], const uint8_t rgb[3]);
 
 /* Render order of split launches (vf_step split form, vf_render, the server): with enable != 0 (the
- * default) a batch of 64 .. 4096 agents is first sorted by (scene id, 2-D Morton code of position) in
+ * default) a batch of 64 .. 1024 agents is first sorted by (scene id, 2-D Morton code of position) in
  * one small kernel, so that the agents one XCD renders share a scene region and its L2 holds the part
  * of the BVH they touch.  The order changes which workgroup renders an agent, never the results. */
 vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);

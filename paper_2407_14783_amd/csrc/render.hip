@@ -431,7 +431,7 @@ hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n,
 }
 
 // Spatial order of a batch (one workgroup): key = scene id, then a 2-D Morton code of the position on a
-// 1024 x 1024 grid over the batch's own bounds; bitonic sort of (key, index) in LDS.  Consecutive
+// 1024 x 1024 grid over the batch's own bounds; each agent's rank counted over the keys in LDS.  Consecutive
 // logical agents -- and so the agents one XCD renders -- then share a scene region, which keeps the
 // part of the BVH each XCD touches small enough for its L2.  The order changes which workgroup renders
 // an agent, never what it renders.
@@ -484,42 +484,26 @@ __global__ void __launch_bounds__(1024) k_order(OrderArgs a) {
         hy = fmaxf(hy, red[3][k]);
     }
     const float sx = hx > lx ? 1023.0f / (hx - lx) : 0.0f, sy = hy > ly ? 1023.0f / (hy - ly) : 0.0f;
-    int m = 1;
-    while (m < a.n) m <<= 1;
-    for (int i = t; i < m; i += blockDim.x) {
-        unsigned long long key = ~0ull;
-        if (i < a.n) {
-            int64_t slot = a.env_idx ? (int64_t)a.env_idx[i] : (int64_t)i;
-            uint32_t code = 0xFFFFFFFFu;
-            if (slot >= 0 && slot < a.n_slots) {
-                float x = a.state[slot * 17], y = a.state[slot * 17 + 1];
-                uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), 1023.0f);
-                uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), 1023.0f);
-                uint32_t sid = (uint32_t)a.views[i].scene_id & 1023u;
-                code = (sid << 20) | spread10(cx) | (spread10(cy) << 1);
-            }
-            key = ((unsigned long long)code << 32) | (uint32_t)i;
+    for (int i = t; i < a.n; i += blockDim.x) {
+        int64_t slot = a.env_idx ? (int64_t)a.env_idx[i] : (int64_t)i;
+        uint32_t code = 0xFFFFFFFFu;
+        if (slot >= 0 && slot < a.n_slots) {
+            float x = a.state[slot * 17], y = a.state[slot * 17 + 1];
+            uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), 1023.0f);
+            uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), 1023.0f);
+            uint32_t sid = (uint32_t)a.views[i].scene_id & 1023u;
+            code = (sid << 20) | spread10(cx) | (spread10(cy) << 1);
         }
-        keys[i] = key;
+        keys[i] = ((unsigned long long)code << 32) | (uint32_t)i;
     }
     __syncthreads();
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < m; i += blockDim.x) {
-                int l = i ^ j;
-                if (l > i) {
-                    unsigned long long x = keys[i], y = keys[l];
-                    bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        keys[i] = y;
-                        keys[l] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    // each agent's rank is the number of smaller keys (keys are distinct: the index is in the low bits)
+    for (int i = t; i < a.n; i += blockDim.x) {
+        const unsigned long long mine = keys[i];
+        int rank = 0;
+        for (int j = 0; j < a.n; ++j) rank += keys[j] < mine ? 1 : 0;
+        a.order[rank] = i;
     }
-    for (int i = t; i < a.n; i += blockDim.x) a.order[i] = (int32_t)(uint32_t)keys[i];
 }
 
 hipError_t launch_order(const OrderArgs& a, hipStream_t st) {

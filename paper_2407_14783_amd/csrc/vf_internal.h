@@ -185,7 +185,7 @@ struct RenderArgs {
     SwarmTable swarm;
     DynConst dyn;
 };
-constexpr int kOrderMax = 4096;      // batches up to this size are put in spatial order
+constexpr int kOrderMax = 1024;      // batches of 64 .. kOrderMax agents are put in spatial order
 struct OrderArgs {
     int32_t n;
     const int32_t* env_idx;
