@@ -368,6 +368,22 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
             c[best] = tv.left[rr];
             c[nk++] = tv.right[rr];
         }
+        // slots still free: split leaf-sized subtrees too (largest area first).  A node tests all four
+        // boxes anyway, so smaller leaves cost no extra box tests and save triangle tests.
+        while (nk < 4) {
+            int best = -1;
+            float besta = -1.0f;
+            for (int k = 0; k < nk; ++k) {
+                if (c[k] >= 0) {
+                    float ar = tv.area(c[k]);
+                    if (ar > besta) { besta = ar; best = k; }
+                }
+            }
+            if (best < 0) break;
+            int32_t rr = c[best];
+            c[best] = tv.left[rr];
+            c[nk++] = tv.right[rr];
+        }
     }
     uint32_t ni = 0;
     for (int k = 0; k < 4; ++k) {
