@@ -331,6 +331,14 @@ vf_status vf_set_stats(vf_ctx* ctx, int32_t enable);
  * out[6] active-lane box tests, out[7] hits.  Synchronises the device. */
 vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset);
 
+/* Render-kernel timing: while enabled (1), vf_step and vf_render record a pair of
+ * HIP events on the caller's stream around every render-kernel launch.
+ * vf_timing_read waits for the recorded events and returns the summed kernel
+ * time (ms) and the number of launches since the last reset.  Disabling clears
+ * the record. */
+vf_status vf_set_timing(vf_ctx* ctx, int32_t enable);
+vf_status vf_timing_read(vf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+
 /* Wait for `stream`, then report (and clear) the sticky device error word:
  * VF_OK, or VF_EDEVICE with the reason in vf_last_error(). */
 vf_status vf_sync_check(vf_ctx* ctx, void* stream);

@@ -202,6 +202,11 @@ vf_status vf_destroy(vf_ctx* ctx) {
     ctx_free(ctx, (void*)ctx->d_labels, sizeof(void*) * kMaxScenes);
     if (ctx->swarm_bytes) ctx_free(ctx, (void*)ctx->swarm.off, ctx->swarm_bytes);
     for (auto& o : ctx->orders) ctx_free(ctx, o.second, kOrderMax * 4);
+    for (auto* list : {&ctx->timing_events, &ctx->timing_free})
+        for (auto& ev : *list) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     ctx_free(ctx, ctx->d_err, 256);
     delete ctx;
     return VF_OK;
@@ -299,6 +304,31 @@ static vf_status check_render_common(vf_ctx* ctx, int64_t n, const float* state,
     return VF_OK;
 }
 
+// Render launch, bracketed by a pair of events on the stream while timing is enabled.
+static hipError_t timed_render(vf_ctx* ctx, const RenderArgs& a, bool fused, hipStream_t st) {
+    if (!ctx->timing) return launch_render(a, fused, ctx->stats, st);
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!ctx->timing_free.empty()) {
+            ev = ctx->timing_free.back();
+            ctx->timing_free.pop_back();
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!ev.first) {
+        e = hipEventCreate(&ev.first);
+        if (e == hipSuccess) e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(ev.first, st);
+    if (e == hipSuccess) e = launch_render(a, fused, ctx->stats, st);
+    if (e == hipSuccess) e = hipEventRecord(ev.second, st);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->timing_events.push_back(ev);
+    return e;
+}
+
 // Agent order scratch of a stream (one per stream, so concurrent streams never share it).
 static int32_t* order_for(vf_ctx* ctx, hipStream_t st) {
     {
@@ -380,7 +410,7 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
         StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
         VF_HIP(launch_step(sa, st));
         maybe_order(ctx, a, st);
-        VF_HIP(launch_render(a, false, ctx->stats, st));
+        VF_HIP(timed_render(ctx, a, false, st));
         return VF_OK;
     }
     int32_t* counters = counters_for(ctx, state, n_slots, &s);
@@ -388,7 +418,7 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     a.action = action;
     a.counters = counters;
     a.dyn = dc;
-    VF_HIP(launch_render(a, true, ctx->stats, st));
+    VF_HIP(timed_render(ctx, a, true, st));
     return VF_OK;
 }
 
@@ -404,7 +434,7 @@ vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float*
     RenderArgs a = make_render_args(ctx, n, env_idx, (float*)state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
                                     out_pixels);
     maybe_order(ctx, a, (hipStream_t)stream);
-    VF_HIP(launch_render(a, false, ctx->stats, (hipStream_t)stream));
+    VF_HIP(timed_render(ctx, a, false, (hipStream_t)stream));
     return VF_OK;
 }
 
@@ -628,6 +658,44 @@ vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset) {
     VF_HIP(hipDeviceSynchronize());
     VF_HIP(hipMemcpy(out, ctx->d_stats, 64, hipMemcpyDeviceToHost));
     if (reset) VF_HIP(hipMemset(ctx->d_stats, 0, 64));
+    return VF_OK;
+}
+
+vf_status vf_set_timing(vf_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_timing: NULL context");
+    VF_HIP(hipSetDevice(ctx->device));
+    if (!enable) {
+        VF_HIP(hipDeviceSynchronize());
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto& ev : ctx->timing_events) ctx->timing_free.push_back(ev);
+        ctx->timing_events.clear();
+    }
+    ctx->timing = enable != 0;
+    return VF_OK;
+}
+
+vf_status vf_timing_read(vf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset) {
+    if (!ctx || !total_ms || !launches) return fail(VF_EINVAL, "vf_timing_read: NULL argument");
+    VF_HIP(hipSetDevice(ctx->device));
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        evs = ctx->timing_events;
+    }
+    double total = 0.0;
+    for (auto& ev : evs) {
+        VF_HIP(hipEventSynchronize(ev.second));
+        float ms = 0.f;
+        VF_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+        total += ms;
+    }
+    *total_ms = total;
+    *launches = (int64_t)evs.size();
+    if (reset) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto& ev : evs) ctx->timing_free.push_back(ev);
+        ctx->timing_events.erase(ctx->timing_events.begin(), ctx->timing_events.begin() + evs.size());
+    }
     return VF_OK;
 }
 

@@ -154,6 +154,9 @@ struct vf_ctx {
     std::vector<vf::Counters> counters;
     vf::SwarmTable swarm{};                // device copy of the swarm lists (n = 0: none)
     int64_t swarm_bytes = 0;
+    bool timing = false;                   // events around every render launch
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;   // recorded pairs
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_free;     // reusable pairs
     bool spatial_order = true;             // render agents in (scene, position) order
     std::vector<std::pair<void*, int32_t*>> orders;   // per stream: [kOrderMax] agent order scratch
 };

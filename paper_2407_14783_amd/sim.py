@@ -264,6 +264,16 @@ class Context:
         """Sort split-launch batches by (scene, position) before rendering (default on)."""
         check(lib.vf_set_spatial_order(self.h, 1 if on else 0), "vf_set_spatial_order")
 
+    def set_timing(self, on):
+        """Record HIP events around every render-kernel launch (see timing_read)."""
+        check(lib.vf_set_timing(self.h, 1 if on else 0), "vf_set_timing")
+
+    def timing_read(self, reset=True):
+        """(summed render-kernel milliseconds, launches) since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib.vf_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0), "vf_timing_read")
+        return ms.value, n.value
+
     def set_stats(self, on):
         check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")
 
