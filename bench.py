@@ -113,9 +113,66 @@ def cpu_baseline(sc, s0, acts, params, budget_s):
                       f"all-triangle ray casting, {frames} frames, {dt:.1f} s)"}
 
 
+def cpu_baseline_extra(params):
+    """The oracle on the other workloads' samples: the full box-room run (1 agent, 100 steps) and one
+    64x64 frame in the smallest and in the largest room graph (20k and 2M triangles)."""
+    from oracle import dynamics as odyn
+    from oracle import render as oren
+    from workloads import agents, scenes
+    out = {}
+    sc = scenes.box_room(seed=1)
+    s = agents.box_room_start(params).astype(np.float64)
+    acts = agents.random_actions(2, 100, 1, params)
+    t0 = time.perf_counter()
+    for k in range(100):
+        s = odyn.step(s, acts[k], params)
+        oren.render_view(s[0], sc, 64, 64, math.pi / 2, with_mask=False)
+    dt = time.perf_counter() - t0
+    out["box_room"] = {"frames_per_s": 100 / dt, "sample": "1 agent x 100 steps, 192 triangles",
+                       "ray_tri_tests_per_s": 100 * 4096 * 192 / dt}
+    scs = scenes.multi_scene_set(seed=6)
+    for j in (0, 7):
+        st = agents.room_graph_starts(60 + j, 1, scs[j], params).astype(np.float64)
+        st = odyn.step(st, agents.random_actions(6, 1, 1, params)[0], params)
+        t0 = time.perf_counter()
+        oren.render_view(st[0], scs[j], 64, 64, math.pi / 2, with_mask=False)
+        dt = time.perf_counter() - t0
+        nt = int(scs[j]["tris"].shape[0])
+        out[f"room_graph_{nt}"] = {"frames_per_s": 1 / dt, "sample": f"1 agent x 1 step, {nt} triangles",
+                                   "ray_tri_tests_per_s_brute_force_equivalent": 4096 * nt / dt}
+    return out
+
+
 def serving_summary(ctx, sim, params):
     from paper_2407_14783_amd import serving
-    return serving.bench_summary(ctx, params)
+    return serving.bench_summary(ctx, params, n_requests=10000)
+
+
+def hover_biased_throughput(ctx, sim, sid, sc, params, n=256, steps=100):
+    """The forest-256 batch under hover-biased actions (c ~ U(0.9, 1.1) g, body rates ~ U(-1, 1)^3), so the
+    agents stay among the trees instead of leaving the forest."""
+    import torch
+    from workloads import agents
+    s0 = agents.forest_starts(4, n, sc, params)
+    acts = torch.as_tensor(agents.random_actions(5, steps, n, params, c_range=(0.9, 1.1), rate=1.0)).cuda()
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+    state = torch.as_tensor(s0).cuda()
+    depth = torch.empty(npx, device="cuda")
+    ids = torch.empty(npx, dtype=torch.int32, device="cuda")
+    p = sim.capi.params_struct(params)
+    for k in range(10):
+        ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "forest-256, hover-biased actions", "ms_per_step": ms, "frames_per_s": n / (ms / 1e3),
+            "hit_fraction": float((ids >= 0).float().mean().item())}
 
 
 def box_room_latency(ctx, sim, params, steps=100):
@@ -279,8 +336,17 @@ def main():
     ctx.sync_check()
     render_ms, render_launches = ctx.timing_read(reset=True)
     ctx.set_timing(False)
+    # four more timed runs of the same K steps (continuing the trajectory) for the run-to-run spread
+    repeats = [gpu_ms_first := e0.elapsed_time(e1)]
+    for _ in range(4):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run(args.warmup, args.warmup + args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        repeats.append(e0.elapsed_time(e1))
     render_s = render_ms / 1e3 / max(render_launches, 1)     # average render-kernel duration
-    gpu_ms = e0.elapsed_time(e1)
+    gpu_ms = gpu_ms_first
     ms_per_step = gpu_ms / args.steps
     frames_per_s = n * args.steps / (gpu_ms / 1e3)
     hit_frac = float((tri_id >= 0).float().mean().item())
@@ -293,6 +359,8 @@ def main():
                       "integrator": "RK4", "dt": params["dt"], "bvh_nodes": int(info["n_nodes"]),
                       "bvh_depth": int(info["depth"]), "scene_build_ms": round(float(info["build_ms"]), 3)},
            "wall_s": wall, "hit_fraction": hit_frac,
+           "ms_per_step_5_runs": {"runs": [r / args.steps for r in repeats],
+                                  "median": float(np.median(repeats)) / args.steps},
            "render_kernel": {"avg_us": render_s * 1e6, "launches": render_launches,
                              "timing": "HIP events around each render launch on its stream, timed region"}}
 
@@ -331,10 +399,12 @@ def main():
         out["serving"] = serving_summary(ctx, sim, params)
     if not args.no_extra:
         out["box_room_latency"] = box_room
+        out["forest256_hover_biased"] = hover_biased_throughput(ctx, sim, sid, sc, params)
         out["multi_scene"] = multi_scene_throughput(ctx, sim, params)
         out["differentiable"] = bptt_throughput(ctx, sim, params)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, s0, acts_np, params, args.cpu_seconds)
+        out["cpu_baseline_other_workloads"] = cpu_baseline_extra(params)
     ctx.free_scene(sid)
     ctx.close()
     print(json.dumps(out))
