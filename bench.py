@@ -323,6 +323,7 @@ def main():
     run(0, args.warmup)
     torch.cuda.synchronize()
     ctx.sync_check()
+    state_at_start = state.clone()      # the timed region starts here; the repeats restart from it
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -336,9 +337,11 @@ def main():
     ctx.sync_check()
     render_ms, render_launches = ctx.timing_read(reset=True)
     ctx.set_timing(False)
-    # four more timed runs of the same K steps (continuing the trajectory) for the run-to-run spread
+    # four more timed runs of the same K steps from the same states, for the run-to-run spread
     repeats = [gpu_ms_first := e0.elapsed_time(e1)]
+    hit_frac = float((tri_id >= 0).float().mean().item())
     for _ in range(4):
+        state.copy_(state_at_start)
         torch.cuda.synchronize()
         e0.record(stream)
         run(args.warmup, args.warmup + args.steps)
@@ -349,7 +352,6 @@ def main():
     gpu_ms = gpu_ms_first
     ms_per_step = gpu_ms / args.steps
     frames_per_s = n * args.steps / (gpu_ms / 1e3)
-    hit_frac = float((tri_id >= 0).float().mean().item())
 
     out = {"metric": METRIC, "value": frames_per_s, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
