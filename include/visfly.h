@@ -118,32 +118,39 @@ typedef struct vf_view {
 /* Summary of a built scene. */
 typedef struct vf_scene_info {
     int64_t n_tris;       /* triangles */
-    int64_t n_nodes;      /* 4-wide BVH nodes */
+    int64_t n_nodes;      /* BVH nodes */
     int64_t n_leaves;     /* leaf slots */
     int64_t bytes;        /* device bytes held (nodes + triangles + colours + index map) */
-    int32_t depth;        /* BVH depth in 4-wide nodes (root = 1) */
+    int32_t depth;        /* BVH depth in nodes (root = 1) */
     int32_t leaf_max;     /* maximum triangles per leaf */
     float bounds_lo[3];   /* scene bounds */
     float bounds_hi[3];
     float build_ms;       /* device time of the build (ms) */
-    int32_t pad;
+    int32_t width;        /* children per node: 4 (vf_bvh4_node) or 8 (vf_bvh8_node) */
 } vf_scene_info;
 
-/* 4-wide BVH node as stored in HBM (128 bytes; for vf_scene_export).
- * child[k] >= 0: index of an inner node; child[k] < 0 with count[k] > 0: leaf
- * of count[k] triangles starting at sorted position first, encoded as
- * -child[k] - 1 = (first << 3) | (count[k] - 1); count[k] == 0 with
- * child[k] < 0 marks an empty slot, whose box is [FLT_MAX, FLT_MAX]^3.  order_lo/order_hi hold, for each of
- * the 8 ray-direction octants o (bit 0: x<0, bit 1: y<0, bit 2: z<0), a byte of
- * four 2-bit child slots in near-to-far order (octant o at bits 8*o..8*o+7 of
- * the 64-bit value order_hi:order_lo). */
+/* BVH node as stored in HBM (for vf_scene_export); vf_scene_info.width says which
+ * layout the library uses.  child[k] >= 0: index of an inner node; child[k] ==
+ * INT32_MIN: empty slot, whose box is [FLT_MAX, FLT_MAX]^3; otherwise a leaf of
+ * ((-child[k] - 1) & 7) + 1 triangles starting at sorted position
+ * (-child[k] - 1) >> 3 (the traversal's stack entry itself).  The orders give,
+ * for each of the 8 ray-direction octants o (bit 0: x<0, bit 1: y<0, bit 2:
+ * z<0), the child slots in near-to-far order.
+ * 4-wide (128 bytes): count[k] is the leaf's triangle count (0 otherwise);
+ * octant o's four 2-bit slots are byte o of the 64-bit order[1]:order[0]. */
 typedef struct vf_bvh4_node {
     float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
     int32_t child[4];
     uint8_t count[4];
-    uint32_t order_lo, order_hi;
-    uint32_t pad;
+    uint32_t order[3];   /* order[2] = 0 */
 } vf_bvh4_node;
+
+/* 8-wide (256 bytes): octant o's eight 3-bit slots are the low 24 bits of order[o]. */
+typedef struct vf_bvh8_node {
+    float lo_x[8], hi_x[8], lo_y[8], hi_y[8], lo_z[8], hi_z[8];
+    int32_t child[8];
+    uint32_t order[8];
+} vf_bvh8_node;
 
 /* Leaf triangle as stored in HBM (48 bytes): v0 and the two edges in float32,
  * and the caller's triangle index (bit pattern in v0w). */
@@ -178,7 +185,7 @@ vf_status vf_scene_free(vf_ctx* ctx, int32_t scene_id);
 /* Counts, bytes and bounds of a scene. */
 vf_status vf_scene_info_get(vf_ctx* ctx, int32_t scene_id, vf_scene_info* out);
 
-/* Copy a scene's BVH nodes (vf_bvh4_node[n_nodes]) and leaf triangles
+/* Copy a scene's BVH nodes (vf_bvh4_node or vf_bvh8_node [n_nodes]) and leaf triangles
  * (vf_tri[n_tris], sorted leaf order) to host buffers (either may be NULL);
  * capacities in bytes.  Synchronous.  For inspection and tests. */
 vf_status vf_scene_export(vf_ctx* ctx, int32_t scene_id, void* nodes_host, int64_t nodes_cap,

@@ -47,7 +47,7 @@ class SceneInfo(ctypes.Structure):
     _fields_ = [("n_tris", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("depth", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("bounds_lo", ctypes.c_float * 3), ("bounds_hi", ctypes.c_float * 3), ("build_ms", ctypes.c_float),
-                ("pad", ctypes.c_int32)]
+                ("width", ctypes.c_int32)]
 
 
 VIEW_DTYPE = np.dtype([("scene_id", "<i4"), ("H", "<i4"), ("W", "<i4"), ("flags", "<i4"), ("hfov", "<f4"),
@@ -55,10 +55,14 @@ VIEW_DTYPE = np.dtype([("scene_id", "<i4"), ("H", "<i4"), ("W", "<i4"), ("flags"
                        ("mount_q", "<f4", 4), ("mount_t", "<f4", 3), ("swarm", "<i4")])
 NODE_DTYPE = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
                        ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<i4", 4), ("count", "u1", 4),
-                       ("order_lo", "<u4"), ("order_hi", "<u4"), ("pad", "<u4")])
+                       ("order", "<u4", 3)])
+NODE8_DTYPE = np.dtype([("lo_x", "<f4", 8), ("hi_x", "<f4", 8), ("lo_y", "<f4", 8), ("hi_y", "<f4", 8),
+                        ("lo_z", "<f4", 8), ("hi_z", "<f4", 8), ("child", "<i4", 8), ("order", "<u4", 8)])
+EMPTY_CHILD = -2 ** 31
 TRI_DTYPE = np.dtype([("v0", "<f4", 3), ("id", "<i4"), ("e1", "<f4", 3), ("pad1", "<f4"), ("e2", "<f4", 3),
                       ("pad2", "<f4")])
 assert VIEW_DTYPE.itemsize == 72 and NODE_DTYPE.itemsize == 128 and TRI_DTYPE.itemsize == 48
+assert NODE8_DTYPE.itemsize == 256
 assert ctypes.sizeof(DynParams) == 128 and ctypes.sizeof(Noise) == 32
 
 

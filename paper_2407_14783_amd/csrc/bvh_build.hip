@@ -344,7 +344,8 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_level) return;
     int32_t r = entries[level_base + e];
-    int32_t c[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+    int32_t c[kWidth];
+    for (int k = 0; k < kWidth; ++k) c[k] = kEmpty;
     int nk;
     if (r == kEmpty) {  // whole scene in one leaf (handled by the host; kept for safety)
         nk = 0;
@@ -353,8 +354,8 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
         c[1] = tv.right[r];
         nk = 2;
         // open the child with the largest surface area among those too big for a leaf, until there
-        // are four (the greedy collapse of a binary tree into a wide one)
-        while (nk < 4) {
+        // are kWidth (the greedy collapse of a binary tree into a wide one)
+        while (nk < kWidth) {
             int best = -1;
             float besta = -1.0f;
             for (int k = 0; k < nk; ++k) {
@@ -368,9 +369,9 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
             c[best] = tv.left[rr];
             c[nk++] = tv.right[rr];
         }
-        // slots still free: split leaf-sized subtrees too (largest area first).  A node tests all four
+        // slots still free: split leaf-sized subtrees too (largest area first).  A node tests all its
         // boxes anyway, so smaller leaves cost no extra box tests and save triangle tests.
-        while (nk < 4) {
+        while (nk < kWidth) {
             int best = -1;
             float besta = -1.0f;
             for (int k = 0; k < nk; ++k) {
@@ -386,8 +387,8 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
         }
     }
     uint32_t ni = 0;
-    for (int k = 0; k < 4; ++k) {
-        kids[4 * (int64_t)e + k] = c[k];
+    for (int k = 0; k < kWidth; ++k) {
+        kids[kWidth * (int64_t)e + k] = c[k];
         if (c[k] != kEmpty && c[k] >= 0 && tv.count(c[k]) > kLeafMax) ++ni;
     }
     n_inner[e] = ni;
@@ -395,57 +396,55 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
 
 __global__ void k_collapse_emit(TreeView tv, int32_t* __restrict__ entries, int32_t level_base, int32_t n_level,
                                 const int32_t* __restrict__ kids, const uint32_t* __restrict__ prefix,
-                                int32_t next_base, Node4* __restrict__ nodes) {
+                                int32_t next_base, Node* __restrict__ nodes) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_level) return;
-    Node4& nd = nodes[level_base + e];
+    Node& nd = nodes[level_base + e];
     uint32_t at = prefix[e];
-    for (int k = 0; k < 4; ++k) {
-        int32_t c = kids[4 * (int64_t)e + k];
+    for (int k = 0; k < kWidth; ++k) {
+        int32_t c = kids[kWidth * (int64_t)e + k];
+        int32_t entry;
         if (c == kEmpty) {
-            nd.child[k] = -1;
-            nd.count[k] = 0;
+            entry = kEmptyChild;
         } else if (c >= 0 && tv.count(c) > kLeafMax) {
-            int32_t idx = next_base + (int32_t)at;
-            entries[idx] = c;
-            nd.child[k] = idx;
-            nd.count[k] = 0;
+            entry = next_base + (int32_t)at;
+            entries[entry] = c;
             ++at;
         } else {
             // a leaf's slot holds the traversal's stack entry: -((first << 3 | (count - 1)) + 1)
-            nd.child[k] = -(((tv.start(c) << 3) | (tv.count(c) - 1)) + 1);
-            nd.count[k] = (uint8_t)tv.count(c);
+            entry = -(((tv.start(c) << 3) | (tv.count(c) - 1)) + 1);
         }
+        nd.child[k] = entry;
+        set_leaf_count(nd, k, leaf_count(entry));
     }
-    nd.pad = 0;
 }
 
 __device__ __forceinline__ float pad_down(float x) { return x - (fabsf(x) + 1.0f) * 1.9073486e-6f; }  // 2^-19
 __device__ __forceinline__ float pad_up(float x) { return x + (fabsf(x) + 1.0f) * 1.9073486e-6f; }
 
-__global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t n_level,
+__global__ void k_bounds(Node* __restrict__ nodes, int32_t level_base, int32_t n_level,
                          const uint32_t* __restrict__ sorted_vals, const float4* __restrict__ tlo,
                          const float4* __restrict__ thi) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_level) return;
-    Node4& nd = nodes[level_base + e];
-    float lo[4][3], hi[4][3];
-    bool valid[4];
-    for (int k = 0; k < 4; ++k) {
+    Node& nd = nodes[level_base + e];
+    float lo[kWidth][3], hi[kWidth][3];
+    bool valid[kWidth];
+    for (int k = 0; k < kWidth; ++k) {
         int32_t c = nd.child[k];
-        int cnt = nd.count[k];
+        int cnt = leaf_count(c);
         float l[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, h[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-        valid[k] = c >= 0 || cnt > 0;
+        valid[k] = c != kEmptyChild;
         if (c >= 0) {
-            const Node4& ch = nodes[c];
-            for (int j = 0; j < 4; ++j) {
-                if (ch.child[j] < 0 && ch.count[j] == 0) continue;
+            const Node& ch = nodes[c];
+            for (int j = 0; j < kWidth; ++j) {
+                if (ch.child[j] == kEmptyChild) continue;
                 l[0] = fminf(l[0], ch.lo_x[j]); h[0] = fmaxf(h[0], ch.hi_x[j]);
                 l[1] = fminf(l[1], ch.lo_y[j]); h[1] = fmaxf(h[1], ch.hi_y[j]);
                 l[2] = fminf(l[2], ch.lo_z[j]); h[2] = fmaxf(h[2], ch.hi_z[j]);
             }
         } else if (cnt > 0) {
-            int f = (-c - 1) >> 3;
+            int f = leaf_first(c);
             for (int j = 0; j < cnt; ++j) {
                 uint32_t t = sorted_vals[f + j];
                 float4 a = tlo[t], b = thi[t];
@@ -456,7 +455,7 @@ __global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t 
         }
         for (int a = 0; a < 3; ++a) { lo[k][a] = l[a]; hi[k][a] = h[a]; }
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kWidth; ++k) {
         // an empty slot gets the box [FLT_MAX, FLT_MAX]^3, which no ray enters
         if (!valid[k])
             for (int a = 0; a < 3; ++a) lo[k][a] = hi[k][a] = FLT_MAX;
@@ -466,46 +465,61 @@ __global__ void k_bounds(Node4* __restrict__ nodes, int32_t level_base, int32_t 
     }
     // near-to-far child order for each ray-direction octant: sort slots by the
     // projection of the box centre on the octant's diagonal; empty slots last
-    uint64_t orders = 0;
+    uint64_t orders4 = 0;
     for (int o = 0; o < 8; ++o) {
         float sx = (o & 1) ? -1.f : 1.f, sy = (o & 2) ? -1.f : 1.f, sz = (o & 4) ? -1.f : 1.f;
-        float key[4];
-        int idx[4] = {0, 1, 2, 3};
-        for (int k = 0; k < 4; ++k)
+        float key[kWidth];
+        int idx[kWidth];
+        for (int k = 0; k < kWidth; ++k) {
+            idx[k] = k;
             key[k] = valid[k] ? sx * (lo[k][0] + hi[k][0]) + sy * (lo[k][1] + hi[k][1]) + sz * (lo[k][2] + hi[k][2])
                               : FLT_MAX;
-        for (int a = 1; a < 4; ++a)
+        }
+        for (int a = 1; a < kWidth; ++a)
             for (int b = a; b > 0 && key[idx[b]] < key[idx[b - 1]]; --b) {
                 int tmp = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = tmp;
             }
-        uint64_t byte = (uint64_t)(idx[0] | (idx[1] << 2) | (idx[2] << 4) | (idx[3] << 6));
-        orders |= byte << (8 * o);
+        uint32_t slots = 0;
+        for (int a = 0; a < kWidth; ++a) slots |= (uint32_t)idx[a] << (kWidthBits * a);
+        if constexpr (kWidth == 4)
+            orders4 |= (uint64_t)slots << (8 * o);
+        else
+            nd.order[o] = slots;
     }
-    nd.order_lo = (uint32_t)orders;
-    nd.order_hi = (uint32_t)(orders >> 32);
+    if constexpr (kWidth == 4) {
+        nd.order[0] = (uint32_t)orders4;
+        nd.order[1] = (uint32_t)(orders4 >> 32);
+        nd.order[2] = 0;
+    }
 }
 
-__global__ void k_single_leaf_root(Node4* __restrict__ nodes, int32_t nt, const float4* __restrict__ tlo,
+__global__ void k_single_leaf_root(Node* __restrict__ nodes, int32_t nt, const float4* __restrict__ tlo,
                                    const float4* __restrict__ thi) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    Node4& nd = nodes[0];
+    Node& nd = nodes[0];
     float l[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, h[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
     for (int t = 0; t < nt; ++t) {
         float4 a = tlo[t], b = thi[t];
         l[0] = fminf(l[0], a.x); l[1] = fminf(l[1], a.y); l[2] = fminf(l[2], a.z);
         h[0] = fmaxf(h[0], b.x); h[1] = fmaxf(h[1], b.y); h[2] = fmaxf(h[2], b.z);
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kWidth; ++k) {
         bool v = k == 0;
         nd.lo_x[k] = v ? pad_down(l[0]) : FLT_MAX; nd.hi_x[k] = v ? pad_up(h[0]) : FLT_MAX;
         nd.lo_y[k] = v ? pad_down(l[1]) : FLT_MAX; nd.hi_y[k] = v ? pad_up(h[1]) : FLT_MAX;
         nd.lo_z[k] = v ? pad_down(l[2]) : FLT_MAX; nd.hi_z[k] = v ? pad_up(h[2]) : FLT_MAX;
-        nd.child[k] = v ? -(((0 << 3) | (nt - 1)) + 1) : -1;
-        nd.count[k] = v ? (uint8_t)nt : 0;
+        nd.child[k] = v ? -(((0 << 3) | (nt - 1)) + 1) : kEmptyChild;
+        set_leaf_count(nd, k, v ? nt : 0);
     }
-    nd.order_lo = 0xE4E4E4E4u;  // identity order 0,1,2,3 for every octant
-    nd.order_hi = 0xE4E4E4E4u;
-    nd.pad = 0;
+    // identity order for every octant
+    uint32_t slots = 0;
+    for (int a = 0; a < kWidth; ++a) slots |= (uint32_t)a << (kWidthBits * a);
+    if constexpr (kWidth == 4) {
+        nd.order[0] = nd.order[1] = slots * 0x01010101u;
+        nd.order[2] = 0;
+    } else {
+        for (int o = 0; o < 8; ++o) nd.order[o] = slots;
+    }
 }
 
 __global__ void k_tri_write(const float* __restrict__ verts, const int32_t* __restrict__ tris,
@@ -576,7 +590,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     GET(keys, nt); GET(vals, nt); GET(keys2, nt); GET(vals2, nt);
     GET(hist, 256 * (int64_t)nb_sort); GET(offs, 256 * (int64_t)nb_sort); GET(total, 4);
     GET(left, nt); GET(right, nt); GET(first, nt); GET(last, nt);
-    GET(entries, nt + 1); GET(kids, 4 * (int64_t)(nt + 1)); GET(n_inner, nt + 1); GET(prefix, nt + 1);
+    GET(entries, nt + 1); GET(kids, kWidth * (int64_t)(nt + 1)); GET(n_inner, nt + 1); GET(prefix, nt + 1);
     int32_t *par_int, *par_leaf;
     uint32_t* flags;
     float4 *nlo, *nhi;
@@ -607,15 +621,15 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
 
     // scene block: nodes | tris | sorted_of | rgb
     const int64_t max_nodes = nt > 1 ? nt : 1;
-    int64_t node_bytes = max_nodes * (int64_t)sizeof(Node4);
+    int64_t node_bytes = max_nodes * (int64_t)sizeof(Node);
     // padded by kLeafMax records: a leaf's triangles are fetched as one fixed-size burst
     int64_t tri_bytes = ((int64_t)nt + kLeafMax) * (int64_t)sizeof(Tri);
     int64_t map_bytes = ((int64_t)nt * 4 + 255) / 256 * 256;
     int64_t rgb_bytes = ((int64_t)nt * 3 + 255) / 256 * 256;
-    Node4* nodes = nullptr;
+    Node* nodes = nullptr;
     // allocate the final block after the topology is known (node count); use a
     // temporary node array of the upper-bound size first
-    Node4* tmp_nodes;
+    Node* tmp_nodes;
     if ((s = sc.get(&tmp_nodes, max_nodes)) != VF_OK) return s;
 
     std::vector<int32_t> level_base, level_n;
@@ -661,11 +675,11 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
             hipLaunchKernelGGL(k_bounds, dim3(blocks_for(level_n[L], 128)), dim3(128), 0, st, tmp_nodes,
                                level_base[L], level_n[L], va == vals ? vals : va, tlo, thi);
     }
-    node_bytes = (int64_t)n_nodes * (int64_t)sizeof(Node4);
+    node_bytes = (int64_t)n_nodes * (int64_t)sizeof(Node);
     int64_t total_bytes = node_bytes + tri_bytes + map_bytes + rgb_bytes;
     void* block = nullptr;
     if ((s = ctx_alloc(ctx, &block, total_bytes)) != VF_OK) return s;
-    nodes = (Node4*)block;
+    nodes = (Node*)block;
     Tri* tri_out = (Tri*)((char*)block + node_bytes);
     int32_t* sorted_of = (int32_t*)((char*)block + node_bytes + tri_bytes);
     uint8_t* rgb_out = (uint8_t*)((char*)block + node_bytes + tri_bytes + map_bytes);
@@ -710,6 +724,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
         out->info.bounds_hi[k] = bnd[9 + k];
     }
     out->info.build_ms = ms;
+    out->info.width = kWidth;
     out->desc.nodes = nodes;
     out->desc.tris = tri_out;
     out->desc.rgb = rgb_out;

@@ -121,18 +121,16 @@ __global__ void __launch_bounds__(128) k_closest_point(QueryArgs q) {
         int32_t e = stack[sp];
         if (sdist[sp] > best) continue;
         if (e >= 0) {
-            const Node4& nd = sc.nodes[e];
-            float dk[4];
-            int32_t ek[4];
+            const Node& nd = sc.nodes[e];
+            float dk[kWidth];
+            int32_t ek[kWidth];
             int nk = 0;
-            for (int k = 0; k < 4; ++k) {
-                int32_t c = nd.child[k];
-                int cnt = nd.count[k];
-                if (c < 0 && cnt == 0) continue;
+            for (int k = 0; k < kWidth; ++k) {
+                const int32_t c = nd.child[k];   // node index, or the leaf's encoded range
+                if (c == kEmptyChild) continue;
                 float d2 = box_dist2(p[0], p[1], p[2], nd.lo_x[k], nd.hi_x[k], nd.lo_y[k], nd.hi_y[k], nd.lo_z[k],
                                      nd.hi_z[k]);
                 if (d2 > best) continue;
-                const int32_t en = c;   // node index, or the leaf's encoded range
                 // insertion into the small list, farthest first
                 int j = nk++;
                 while (j > 0 && dk[j - 1] < d2) {
@@ -141,7 +139,7 @@ __global__ void __launch_bounds__(128) k_closest_point(QueryArgs q) {
                     --j;
                 }
                 dk[j] = d2;
-                ek[j] = en;
+                ek[j] = c;
             }
             for (int j = 0; j < nk; ++j) {
                 if (sp < kQueryStack) {

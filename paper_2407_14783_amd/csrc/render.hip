@@ -61,7 +61,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                                              const float (&d)[NR][3], float t_near, float t_far,
                                              float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
                                              TraceStats& ts) {
-    const Node4 CONST_AS* nodes = (const Node4 CONST_AS*)sc.nodes;
+    const Node CONST_AS* nodes = (const Node CONST_AS*)sc.nodes;
     const Tri CONST_AS* tris = (const Tri CONST_AS*)sc.tris;
     float inv[NR][3], oi[NR][3];
     int n_valid = 0;
@@ -98,22 +98,29 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
         if (entry >= 0) {
             // the whole 128-byte node in one burst of wave-uniform (scalar) loads
             const uint32_t CONST_AS* np = (const uint32_t CONST_AS*)(nodes + entry);
-            uint32_t w[32];
+            uint32_t w[kNodeWords];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) w[i] = np[i];
-            asm volatile("" ::"s"(w[28]), "s"(w[31]));   // unused words: keeps two 16-dword loads
+            for (int i = 0; i < kNodeWords; ++i) w[i] = np[i];
+            // words the traversal may not read (leaf counts, padding, other octants' orders): naming
+            // them keeps the node one run of 16-dword loads
+            if constexpr (kWidth == 4) {
+                asm volatile("" ::"s"(w[28]), "s"(w[31]));
+            } else {
+#pragma unroll
+                for (int i = kOrderWord; i < kNodeWords; ++i) asm volatile("" ::"s"(w[i]));
+            }
             if (STATS) {
                 ts.node_wave += 1;
                 ts.node_lane += n_valid;
-                ts.box_lane += 4 * n_valid;
+                ts.box_lane += kWidth * n_valid;
             }
             // bit k: some ray of the packet enters child k's box (empty slots hold a box no ray enters)
             uint32_t hb = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float lox = __uint_as_float(w[k]), hix = __uint_as_float(w[4 + k]);
-                const float loy = __uint_as_float(w[8 + k]), hiy = __uint_as_float(w[12 + k]);
-                const float loz = __uint_as_float(w[16 + k]), hiz = __uint_as_float(w[20 + k]);
+            for (int k = 0; k < kWidth; ++k) {
+                const float lox = __uint_as_float(w[k]), hix = __uint_as_float(w[kWidth + k]);
+                const float loy = __uint_as_float(w[2 * kWidth + k]), hiy = __uint_as_float(w[3 * kWidth + k]);
+                const float loz = __uint_as_float(w[4 * kWidth + k]), hiz = __uint_as_float(w[5 * kWidth + k]);
                 uint64_t m = 0;   // lanes with a ray entering the box (the union over the lane's rays)
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -128,17 +135,33 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 }
                 hb |= (m != 0ull ? 1u : 0u) << k;
             }
-            const uint64_t ord = ((uint64_t)w[30] << 32) | w[29];
-            const uint32_t byte = (uint32_t)(ord >> (8 * oct)) & 255u;
+            // the octant's child slots, near to far
+            uint32_t slots;
+            if constexpr (kWidth == 4) {
+                const uint64_t ord = ((uint64_t)w[kOrderWord + 1] << 32) | w[kOrderWord];
+                slots = (uint32_t)(ord >> (8 * oct)) & 255u;
+            } else {
+                const uint32_t o01 = (oct & 1) ? w[kOrderWord + 1] : w[kOrderWord];
+                const uint32_t o23 = (oct & 1) ? w[kOrderWord + 3] : w[kOrderWord + 2];
+                const uint32_t o45 = (oct & 1) ? w[kOrderWord + 5] : w[kOrderWord + 4];
+                const uint32_t o67 = (oct & 1) ? w[kOrderWord + 7] : w[kOrderWord + 6];
+                const uint32_t o03 = (oct & 2) ? o23 : o01, o47 = (oct & 2) ? o67 : o45;
+                slots = (oct & 4) ? o47 : o03;
+            }
             // push hit children far-to-near so the nearest is on top
 #pragma unroll
-            for (int i = 3; i >= 0; --i) {
-                const uint32_t k = (byte >> (2 * i)) & 3u;
+            for (int i = kWidth - 1; i >= 0; --i) {
+                const uint32_t k = (slots >> (kWidthBits * i)) & (uint32_t)(kWidth - 1);
                 if ((hb >> k) & 1u) {
                     // the slot word is the stack entry: a node index, or the leaf's encoded range
-                    const int32_t e01 = (int32_t)((k & 1u) ? w[25] : w[24]);
-                    const int32_t e23 = (int32_t)((k & 1u) ? w[27] : w[26]);
-                    const int32_t e = (k & 2u) ? e23 : e01;
+                    const int32_t e01 = (int32_t)((k & 1u) ? w[kChildWord + 1] : w[kChildWord]);
+                    const int32_t e23 = (int32_t)((k & 1u) ? w[kChildWord + 3] : w[kChildWord + 2]);
+                    int32_t e = (k & 2u) ? e23 : e01;
+                    if constexpr (kWidth == 8) {
+                        const int32_t e45 = (int32_t)((k & 1u) ? w[kChildWord + 5] : w[kChildWord + 4]);
+                        const int32_t e67 = (int32_t)((k & 1u) ? w[kChildWord + 7] : w[kChildWord + 6]);
+                        e = (k & 4u) ? ((k & 2u) ? e67 : e45) : e;
+                    }
                     // write lane sp of the two stack registers (lane compares + selects, no branch);
                     // the depth limit of the build bounds sp below kStackCap
                     stk0 = lane_id() == sp ? e : stk0;
@@ -273,7 +296,7 @@ __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) 
 }
 
 template <bool FUSED, bool STATS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
 k_render(RenderArgs a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;

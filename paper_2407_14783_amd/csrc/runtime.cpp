@@ -275,7 +275,7 @@ vf_status vf_scene_export(vf_ctx* ctx, int32_t scene_id, void* nodes_host, int64
         return fail(VF_ENOSCENE, "vf_scene_export: no such scene");
     VF_HIP(hipSetDevice(ctx->device));
     const SceneHost& s = ctx->scenes[scene_id];
-    int64_t nb = s.info.n_nodes * (int64_t)sizeof(Node4), tb = s.info.n_tris * (int64_t)sizeof(Tri);
+    int64_t nb = s.info.n_nodes * (int64_t)sizeof(Node), tb = s.info.n_tris * (int64_t)sizeof(Tri);
     if (nodes_host) {
         if (nodes_cap < nb) return fail(VF_EINVAL, "vf_scene_export: node buffer too small");
         VF_HIP(hipMemcpy(nodes_host, s.desc.nodes, nb, hipMemcpyDeviceToHost));

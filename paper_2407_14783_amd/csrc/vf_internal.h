@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -31,10 +32,20 @@ constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 #define VF_LEAF_MAX 4
 #endif
 constexpr int kLeafMax = VF_LEAF_MAX;  // triangles per BVH leaf (at most 8: the stack entry keeps 3 bits)
+#ifndef VF_BVH_WIDTH
+#define VF_BVH_WIDTH 4
+#endif
+constexpr int kWidth = VF_BVH_WIDTH;                 // children per BVH node
+static_assert(kWidth == 4 || kWidth == 8, "4- or 8-wide BVH");
+constexpr int kWidthBits = kWidth == 4 ? 2 : 3;      // bits of a child slot index
+// waves per SIMD the render kernel is compiled for: the 8-wide node needs 64 scalar registers
+// for one node, which 8 waves per SIMD cannot hold besides the rest
+constexpr int kRenderWavesPerEu = kWidth == 4 ? 8 : 6;
 constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
-constexpr int kMaxBvhDepth = 40;      // builds deeper than this are rejected (3 pushes per level)
-// a packet keeps at most 3 pending siblings per level of its path plus the 4 children just pushed
-static_assert(3 * (kMaxBvhDepth - 1) + 4 <= kStackCap, "traversal stack cannot overflow");
+// builds deeper than this are rejected: a packet keeps at most kWidth - 1 pending siblings per level
+constexpr int kMaxBvhDepth = kWidth == 4 ? 40 : 18;
+// a packet keeps at most kWidth - 1 pending siblings per level of its path plus the children just pushed
+static_assert((kWidth - 1) * (kMaxBvhDepth - 1) + kWidth <= kStackCap, "traversal stack cannot overflow");
 constexpr int kMaxScenes = 1024;
 constexpr int kMaxImage = 1024;
 
@@ -52,15 +63,33 @@ enum : uint32_t {
 // ---------------------------------------------------------------------------
 // device scene layout
 // ---------------------------------------------------------------------------
+// A BVH node: SoA child boxes, one stack entry per child (node index, or a leaf's encoded range, or
+// kEmptyChild), and the near-to-far child order of each of the 8 ray-direction octants.
+//   4-wide (128 B): + leaf counts (byte per child) and the orders as one 64-bit value (a byte per octant)
+//   8-wide (256 B): the orders as 8 words (octant o: 3-bit slots in word o)
+constexpr int32_t kEmptyChild = INT32_MIN;
 struct alignas(16) Node4 {
     float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
     int32_t child[4];
     uint8_t count[4];
-    uint32_t order_lo, order_hi;
-    uint32_t pad;
+    uint32_t order[3];   // order[0] | order[1] << 32: byte o = octant o's slots; order[2] = 0
 };
-static_assert(sizeof(Node4) == 128, "node is two 64-byte lines");
-static_assert(sizeof(Node4) == sizeof(vf_bvh4_node), "node matches the exported layout");
+struct alignas(16) Node8 {
+    float lo_x[8], hi_x[8], lo_y[8], hi_y[8], lo_z[8], hi_z[8];
+    int32_t child[8];
+    uint32_t order[8];   // word o: octant o's eight 3-bit slots
+};
+static_assert(sizeof(Node4) == 128 && sizeof(Node4) == sizeof(vf_bvh4_node), "4-wide node layout");
+static_assert(sizeof(Node8) == 256 && sizeof(Node8) == sizeof(vf_bvh8_node), "8-wide node layout");
+using Node = typename std::conditional<kWidth == 4, Node4, Node8>::type;
+constexpr int kNodeWords = (int)sizeof(Node) / 4;
+constexpr int kChildWord = 6 * kWidth;                     // first child word
+constexpr int kOrderWord = kWidth == 4 ? 29 : 56;          // first order word
+// leaf count of a child entry (0 for an inner node or an empty slot)
+__host__ __device__ inline int leaf_count(int32_t c) { return (c < 0 && c != kEmptyChild) ? ((-c - 1) & 7) + 1 : 0; }
+__host__ __device__ inline int leaf_first(int32_t c) { return (-c - 1) >> 3; }
+__host__ __device__ inline void set_leaf_count(Node4& n, int k, int c) { n.count[k] = (uint8_t)c; }
+__host__ __device__ inline void set_leaf_count(Node8&, int, int) {}
 
 struct alignas(16) Tri {
     float v0x, v0y, v0z; int32_t id;
@@ -72,7 +101,7 @@ static_assert(sizeof(Tri) == sizeof(vf_tri), "triangle matches the exported layo
 
 // One entry of the device scene table (64 bytes).
 struct alignas(16) SceneDesc {
-    const Node4* nodes;
+    const Node* nodes;
     const Tri* tris;          // sorted leaf order
     const uint8_t* rgb;       // [T][3] caller order, or null
     const int32_t* sorted_of; // caller triangle index -> sorted position

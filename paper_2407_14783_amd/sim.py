@@ -104,11 +104,11 @@ class Context:
         check(lib.vf_scene_info_get(self.h, sid, ctypes.byref(info)), "vf_scene_info_get")
         return {"n_tris": info.n_tris, "n_nodes": info.n_nodes, "bytes": info.bytes, "depth": info.depth,
                 "leaf_max": info.leaf_max, "bounds_lo": list(info.bounds_lo), "bounds_hi": list(info.bounds_hi),
-                "build_ms": info.build_ms}
+                "build_ms": info.build_ms, "width": info.width}
 
     def export_scene(self, sid):
         info = self.scene_info(sid)
-        nodes = np.zeros(info["n_nodes"], dtype=capi.NODE_DTYPE)
+        nodes = np.zeros(info["n_nodes"], dtype=capi.NODE_DTYPE if info["width"] == 4 else capi.NODE8_DTYPE)
         tris = np.zeros(info["n_tris"], dtype=capi.TRI_DTYPE)
         check(lib.vf_scene_export(self.h, sid, nodes.ctypes.data_as(ctypes.c_void_p), nodes.nbytes,
                                   tris.ctypes.data_as(ctypes.c_void_p), tris.nbytes), "vf_scene_export")

@@ -38,6 +38,9 @@ def test_struct_layouts_match_header():
     assert capi.VIEW_DTYPE.fields["swarm"][1] == 68
     assert capi.NODE_DTYPE.itemsize == 128 and capi.TRI_DTYPE.itemsize == 48
     assert capi.NODE_DTYPE.fields["child"][1] == 96 and capi.NODE_DTYPE.fields["count"][1] == 112
+    assert capi.NODE_DTYPE.fields["order"][1] == 116
+    assert capi.NODE8_DTYPE.itemsize == 256 and capi.NODE8_DTYPE.fields["child"][1] == 192
+    assert capi.NODE8_DTYPE.fields["order"][1] == 224
 
 
 def test_params_struct_roundtrip():

@@ -470,23 +470,38 @@ def test_bvh_invariants_and_deterministic_rebuild(vf):
     covered = np.zeros(T, dtype=np.int64)
     lo = np.stack([nodes["lo_x"], nodes["lo_y"], nodes["lo_z"]], -1)
     hi = np.stack([nodes["hi_x"], nodes["hi_y"], nodes["hi_z"]], -1)
+    width = info["width"]
+    assert width in (4, 8) and nodes["child"].shape[1] == width
+    empty = -2 ** 31
     for ni in range(len(nodes)):
-        for k in range(4):
-            c, cnt = nodes["child"][ni, k], nodes["count"][ni, k]
+        for k in range(width):
+            c = int(nodes["child"][ni, k])
             if c >= 0:
                 assert c > ni
-                valid = (nodes["child"][c] >= 0) | (nodes["count"][c] > 0)
+                valid = nodes["child"][c] != empty
                 assert np.all(lo[c][valid] >= lo[ni, k]) and np.all(hi[c][valid] <= hi[ni, k])
-            elif cnt > 0:
-                f = (-c - 1) >> 3
-                assert ((-c - 1) & 7) + 1 == cnt
+            elif c != empty:
+                f, cnt = (-c - 1) >> 3, ((-c - 1) & 7) + 1
+                if width == 4:
+                    assert nodes["count"][ni, k] == cnt
                 covered[f:f + cnt] += 1
                 ids = tris["id"][f:f + cnt]
                 tv = v[t[ids]].reshape(-1, 3)
                 assert np.all(tv >= lo[ni, k]) and np.all(tv <= hi[ni, k])
+            else:                            # an empty slot's box never meets a ray
+                assert np.all(lo[ni, k] > 1e37) and np.all(hi[ni, k] > 1e37)
+        # every octant's order is a permutation of the slots
+        if width == 4:
+            words = nodes["order"][ni]
+            packed = int(words[0]) | (int(words[1]) << 32)
+            perms = [[(packed >> (8 * o + 2 * i)) & 3 for i in range(4)] for o in range(8)]
+        else:
+            perms = [[(int(nodes["order"][ni, o]) >> (3 * i)) & 7 for i in range(8)] for o in range(8)]
+        for perm in perms:
+            assert sorted(perm) == list(range(width))
     assert np.all(covered == 1)
     # root bounds contain the scene
-    valid0 = (nodes["child"][0] >= 0) | (nodes["count"][0] > 0)
+    valid0 = nodes["child"][0] != empty
     assert np.all(lo[0][valid0].min(0) <= v.min(0)) and np.all(hi[0][valid0].max(0) >= v.max(0))
     assert info["depth"] >= 2 and info["n_nodes"] == len(nodes)
     sid2 = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
