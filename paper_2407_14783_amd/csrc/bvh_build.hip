@@ -4,13 +4,16 @@
 // Pipeline (all on the caller's stream, one scene at a time):
 //   1. tri_prep      per-triangle bounds and centroid, block partial bounds
 //   2. reduce        centroid and scene bounds
-//   3. morton        30-bit Morton code of the quantised centroid, value = index
+//   3. morton        30-bit Morton code of the centroid quantised in the cube around
+//                    all centroids (one scale for the three axes), value = index
 //   4. radix sort    stable LSD, 8-bit digits, 4 passes (histogram / scan / scatter)
 //   5. radix tree    binary radix tree over the sorted codes (Karras, HPG 2012),
-//                    duplicate codes split by index
-//   6. collapse      level by level: each 4-wide node takes the two children of its
-//                    binary node and repeatedly opens the child with the most
-//                    triangles until it has four; children with <= kLeafMax
+//                    duplicate codes split by index; parent links, then the binary
+//                    boxes bottom-up (one climb per leaf, the second arrival goes on)
+//   6. collapse      level by level: each wide node takes the two children of its
+//                    binary node and opens the child of largest surface area among
+//                    those too big for a leaf until it has kWidth; free slots are then
+//                    filled by splitting leaf-sized subtrees; children with <= kLeafMax
 //                    triangles become leaves (a contiguous sorted range)
 //   7. bounds        bottom-up per level (deepest first), leaf boxes padded by a
 //                    few ulps, plus per-octant near-to-far child orders
@@ -121,6 +124,10 @@ __global__ void k_morton(const float4* __restrict__ cen, int32_t nt, const float
     float4 c = cen[t];
     float lo[3] = {bounds[0], bounds[1], bounds[2]};
     float ext[3] = {bounds[3] - lo[0], bounds[4] - lo[1], bounds[5] - lo[2]};
+    // one scale for all axes (the cube around the centroids): a flat scene is then split along its
+    // long axes first, not the same number of times along each axis
+    const float e = fmaxf(ext[0], fmaxf(ext[1], ext[2]));
+    ext[0] = ext[1] = ext[2] = e;
     float cc[3] = {c.x, c.y, c.z};
     uint32_t q[3];
     for (int k = 0; k < 3; ++k) {
