@@ -69,9 +69,13 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 5}))
 
 
+TRAFFIC_SOURCES = ("render.hip", "vf_internal.h", "dynamics.h", "bvh_build.hip")
+
+
 def committed_traffic():
     """(fetch_kib, write_kib) per dispatch from profiles/render_forest256_pmc.md if the render kernel's
-    sources still hash as when the counters were taken, else None."""
+    sources and the BVH build (which lays out what it reads) still hash as when the counters were taken,
+    else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "render_forest256_pmc.md")
     if not os.path.exists(path):
@@ -82,7 +86,7 @@ def committed_traffic():
     kv = dict(tok.split("=") for tok in line[0].split(":", 1)[1].split())
     csrc = os.path.join(ROOT, "paper_2407_14783_amd", "csrc")
     h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                for f in ("render.hip", "vf_internal.h", "dynamics.h"))).hexdigest()[:16]
+                                for f in TRAFFIC_SOURCES)).hexdigest()[:16]
     if h != kv.get("source_sha256_16"):
         return None
     return float(kv["fetch"]), float(kv["write"])

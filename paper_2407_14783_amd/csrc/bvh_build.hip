@@ -142,25 +142,25 @@ __global__ void k_morton(const float4* __restrict__ cen, int32_t nt, const float
 // ---------------------------------------------------------------------------
 // exclusive scan (single workgroup; used for the sort histograms and the collapse)
 // ---------------------------------------------------------------------------
-__global__ void k_scan_exclusive(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
-                                 uint32_t* __restrict__ total) {
-    __shared__ uint32_t sums[kScanThreads];
+template <class T>
+__global__ void k_scan_exclusive(const T* __restrict__ in, T* __restrict__ out, int64_t n, T* __restrict__ total) {
+    __shared__ T sums[kScanThreads];
     int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
     int64_t b = threadIdx.x * chunk, e = b + chunk < n ? b + chunk : n;
-    uint32_t s = 0;
+    T s = 0;
     for (int64_t i = b; i < e; ++i) s += in[i];
     sums[threadIdx.x] = s;
     __syncthreads();
     // Hillis-Steele inclusive scan of the chunk sums
     for (int off = 1; off < kScanThreads; off <<= 1) {
-        uint32_t v = (int)threadIdx.x >= off ? sums[threadIdx.x - off] : 0u;
+        T v = (int)threadIdx.x >= off ? sums[threadIdx.x - off] : (T)0;
         __syncthreads();
         sums[threadIdx.x] += v;
         __syncthreads();
     }
-    uint32_t run = threadIdx.x > 0 ? sums[threadIdx.x - 1] : 0u;
+    T run = threadIdx.x > 0 ? sums[threadIdx.x - 1] : (T)0;
     for (int64_t i = b; i < e; ++i) {
-        uint32_t v = in[i];
+        T v = in[i];
         out[i] = run;
         run += v;
     }
@@ -323,6 +323,134 @@ __global__ void k_binary_bounds(const int32_t* __restrict__ left, const int32_t*
         nhi[p] = make_float4(h[0], h[1], h[2], 0.f);
         p = par_int[p];
     }
+}
+
+// ---------------------------------------------------------------------------
+// binary tree by locally-ordered clustering (PLOC: Meister and Bittner, IEEE TVCG 2018).
+// Clusters start as the leaves in Morton order.  Each pass, every cluster finds the
+// neighbour within kPlocRadius positions whose merged box has the smallest surface
+// area; mutual pairs merge into a new inner node placed at the lower position, and
+// the cluster array is compacted.  Pairs are ordered by (area, lower index, higher
+// index), so the globally best pair is always mutual and every pass merges at least
+// once.  Inner nodes are numbered by pass and prefix sum (deterministic); a node's
+// children are always from earlier passes, which the top-down range pass relies on.
+// Child references: inner node k >= 0, leaf -(i + 1) for Morton position i; after
+// the range pass leaves are renumbered to depth-first order, so every subtree is a
+// contiguous range of the leaf array (what the collapse and the leaf encoding need).
+// ---------------------------------------------------------------------------
+#ifndef VF_PLOC_RADIUS
+#define VF_PLOC_RADIUS 6
+#endif
+constexpr int kPlocRadius = VF_PLOC_RADIUS;
+
+__device__ __forceinline__ float merged_area(float4 alo, float4 ahi, float4 blo, float4 bhi) {
+    const float dx = fmaxf(ahi.x, bhi.x) - fminf(alo.x, blo.x);
+    const float dy = fmaxf(ahi.y, bhi.y) - fminf(alo.y, blo.y);
+    const float dz = fmaxf(ahi.z, bhi.z) - fminf(alo.z, blo.z);
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_init(const uint32_t* __restrict__ sorted_vals, int32_t nt, const float4* __restrict__ tlo,
+                            const float4* __restrict__ thi, int32_t* __restrict__ cid, float4* __restrict__ clo,
+                            float4* __restrict__ chi) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const uint32_t t = sorted_vals[i];
+    cid[i] = -(i + 1);
+    clo[i] = tlo[t];
+    chi[i] = thi[t];
+}
+
+// nearest neighbour of each of the m >= 2 clusters; on equal areas the lower index wins, which
+// with a fixed i is the (lower index, higher index) order of the pair
+__global__ void k_ploc_nn(int32_t m, const float4* __restrict__ clo, const float4* __restrict__ chi,
+                          int32_t* __restrict__ nn) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const float4 l = clo[i], h = chi[i];
+    const int j0 = i - kPlocRadius > 0 ? i - kPlocRadius : 0;
+    const int j1 = i + kPlocRadius < m - 1 ? i + kPlocRadius : m - 1;
+    int bj = -1;
+    float ba = 0.f;
+    for (int j = j0; j <= j1; ++j) {
+        if (j == i) continue;
+        const float a = merged_area(l, h, clo[j], chi[j]);
+        if (bj < 0 || a < ba) { ba = a; bj = j; }
+    }
+    nn[i] = bj;   // m >= 2: some j exists
+}
+
+// per cluster: bit 32 = it survives the pass, bit 0 = it is the lower member of a mutual pair
+__global__ void k_ploc_flags(int32_t m, const int32_t* __restrict__ nn, uint64_t* __restrict__ fl) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t j = nn[i];
+    const bool mutual = nn[j] == i;
+    const uint64_t keep = (mutual && j < i) ? 0u : 1u;
+    const uint64_t merge = (mutual && i < j) ? 1u : 0u;
+    fl[i] = (keep << 32) | merge;
+}
+
+__global__ void k_ploc_merge(int32_t m, const int32_t* __restrict__ nn, const uint64_t* __restrict__ fl,
+                             const uint64_t* __restrict__ pre, int32_t node_base, const int32_t* __restrict__ cid,
+                             const float4* __restrict__ clo, const float4* __restrict__ chi,
+                             int32_t* __restrict__ cid2, float4* __restrict__ clo2, float4* __restrict__ chi2,
+                             int32_t* __restrict__ left, int32_t* __restrict__ right, int32_t* __restrict__ cnt,
+                             float4* __restrict__ nlo, float4* __restrict__ nhi) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t f = fl[i];
+    if (!(f >> 32)) return;
+    const int32_t pos = (int32_t)(pre[i] >> 32);
+    if (f & 1u) {
+        const int32_t j = nn[i];
+        const int32_t k = node_base + (int32_t)(pre[i] & 0xffffffffu);
+        const int32_t a = cid[i], b = cid[j];
+        const float4 al = clo[i], ah = chi[i], bl = clo[j], bh = chi[j];
+        const float4 lo = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.f);
+        const float4 hi = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.f);
+        left[k] = a;
+        right[k] = b;
+        cnt[k] = (a >= 0 ? cnt[a] : 1) + (b >= 0 ? cnt[b] : 1);
+        nlo[k] = lo;
+        nhi[k] = hi;
+        cid2[pos] = k;
+        clo2[pos] = lo;
+        chi2[pos] = hi;
+    } else {
+        cid2[pos] = cid[i];
+        clo2[pos] = clo[i];
+        chi2[pos] = chi[i];
+    }
+}
+
+// top-down: the inner nodes of one pass [k0, k1) hand their depth-first leaf offsets to their children
+__global__ void k_ploc_offsets(int32_t k0, int32_t k1, const int32_t* __restrict__ left,
+                               const int32_t* __restrict__ right, const int32_t* __restrict__ cnt,
+                               int32_t* __restrict__ off, int32_t* __restrict__ newpos) {
+    int k = k0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k1) return;
+    const int32_t o = off[k], a = left[k], b = right[k];
+    const int32_t ob = o + (a >= 0 ? cnt[a] : 1);
+    if (a >= 0) off[a] = o; else newpos[-a - 1] = o;
+    if (b >= 0) off[b] = ob; else newpos[-b - 1] = ob;
+}
+
+// leaf ranges of the inner nodes, leaves renumbered to depth-first order, triangle order to match
+__global__ void k_ploc_finish(int32_t nt, int32_t* __restrict__ left, int32_t* __restrict__ right,
+                              const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                              const int32_t* __restrict__ newpos, int32_t* __restrict__ first,
+                              int32_t* __restrict__ last, const uint32_t* __restrict__ sorted_vals,
+                              uint32_t* __restrict__ dfs_vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    dfs_vals[newpos[i]] = sorted_vals[i];
+    if (i >= nt - 1) return;
+    first[i] = off[i];
+    last[i] = off[i] + cnt[i] - 1;
+    const int32_t a = left[i], b = right[i];
+    if (a < 0) left[i] = -(newpos[-a - 1] + 1);
+    if (b < 0) right[i] = -(newpos[-b - 1] + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -616,7 +744,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     uint32_t *ka = keys, *va = vals, *kb = keys2, *vb = vals2;
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, nt, shift, hist, nb_sort);
-        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(kScanThreads), 0, st, hist, offs, 256 * (int64_t)nb_sort,
+        hipLaunchKernelGGL(k_scan_exclusive<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, hist, offs, 256 * (int64_t)nb_sort,
                            (uint32_t*)nullptr);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, va, kb, vb, nt, shift, offs,
                            nb_sort);
@@ -641,6 +769,9 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
 
     std::vector<int32_t> level_base, level_n;
     int depth = 0;
+    // triangle of each leaf position: Morton order, or depth-first order of the clustered tree
+    const uint32_t* leaf_vals = vals;
+    uint32_t* dfs_vals = nullptr;
     int32_t n_nodes = 0;
     bool single_leaf = nt <= kLeafMax;
     if (single_leaf) {
@@ -648,39 +779,104 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
         n_nodes = 1;
         depth = 1;
     } else {
-        hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, ka, nt, left, right, first,
-                           last);
-        hipLaunchKernelGGL(k_parents, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, left, right, nt, par_int,
-                           par_leaf);
-        VF_HIP(hipMemsetAsync(flags, 0, (size_t)nt * 4, st));
-        hipLaunchKernelGGL(k_binary_bounds, dim3(blocks_for(nt, 256)), dim3(256), 0, st, left, right, nt, vals, tlo,
-                           thi, par_int, par_leaf, flags, nlo, nhi);
         TreeView tv{left, right, first, last, nlo, nhi};
-        int32_t root = 0;
-        VF_HIP(hipMemcpyAsync(entries, &root, sizeof(int32_t), hipMemcpyHostToDevice, st));
-        int32_t base = 0, n_level = 1;
-        while (n_level > 0) {
-            if (depth >= kMaxBvhDepth) return fail(VF_EINVAL, "scene BVH deeper than the traversal stack allows");
-            level_base.push_back(base);
-            level_n.push_back(n_level);
-            ++depth;
-            hipLaunchKernelGGL(k_collapse_count, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries, base,
-                               n_level, kids, n_inner);
-            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(kScanThreads), 0, st, n_inner, prefix,
-                               (int64_t)n_level, total);
-            int32_t next_base = base + n_level;
-            hipLaunchKernelGGL(k_collapse_emit, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries, base,
-                               n_level, kids, prefix, next_base, tmp_nodes);
-            uint32_t nnext = 0;
-            VF_HIP(hipMemcpyAsync(&nnext, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            VF_HIP(hipStreamSynchronize(st));
-            base = next_base;
-            n_level = (int32_t)nnext;
+        // collapse the binary tree below `root` level by level; *too_deep when the wide tree would
+        // exceed the traversal's depth bound
+        auto collapse = [&](int32_t root, const uint32_t* leaf_vals, bool* too_deep) -> vf_status {
+            *too_deep = false;
+            level_base.clear();
+            level_n.clear();
+            depth = 0;
+            VF_HIP(hipMemcpyAsync(entries, &root, sizeof(int32_t), hipMemcpyHostToDevice, st));
+            int32_t base = 0, n_level = 1;
+            while (n_level > 0) {
+                if (depth >= kMaxBvhDepth) {
+                    *too_deep = true;
+                    return VF_OK;
+                }
+                level_base.push_back(base);
+                level_n.push_back(n_level);
+                ++depth;
+                hipLaunchKernelGGL(k_collapse_count, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries,
+                                   base, n_level, kids, n_inner);
+                hipLaunchKernelGGL(k_scan_exclusive<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, n_inner, prefix,
+                                   (int64_t)n_level, total);
+                int32_t next_base = base + n_level;
+                hipLaunchKernelGGL(k_collapse_emit, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries,
+                                   base, n_level, kids, prefix, next_base, tmp_nodes);
+                uint32_t nnext = 0;
+                VF_HIP(hipMemcpyAsync(&nnext, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                VF_HIP(hipStreamSynchronize(st));
+                base = next_base;
+                n_level = (int32_t)nnext;
+            }
+            n_nodes = base;
+            for (int L = depth - 1; L >= 0; --L)
+                hipLaunchKernelGGL(k_bounds, dim3(blocks_for(level_n[L], 128)), dim3(128), 0, st, tmp_nodes,
+                                   level_base[L], level_n[L], leaf_vals, tlo, thi);
+            return VF_OK;
+        };
+        bool too_deep = true;
+        if (kBvhPloc) {
+            int32_t *cid, *cid2, *nn, *cnt, *off, *newpos;
+            float4 *clo, *chi, *clo2, *chi2;
+            uint64_t *fl, *pre, *tot64;
+#define GET(p, n) if ((s = sc.get(&p, n)) != VF_OK) return s
+            GET(cid, nt); GET(cid2, nt); GET(nn, nt); GET(cnt, nt); GET(off, nt); GET(newpos, nt);
+            GET(clo, nt); GET(chi, nt); GET(clo2, nt); GET(chi2, nt); GET(fl, nt); GET(pre, nt); GET(tot64, 1);
+            GET(dfs_vals, nt);
+#undef GET
+            hipLaunchKernelGGL(k_ploc_init, dim3(blocks_for(nt, 256)), dim3(256), 0, st, vals, nt, tlo, thi, cid, clo,
+                               chi);
+            std::vector<int32_t> pass_base;
+            int32_t m = nt, node_base = 0;
+            while (m > 1) {
+                hipLaunchKernelGGL(k_ploc_nn, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, clo, chi, nn);
+                hipLaunchKernelGGL(k_ploc_flags, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl);
+                hipLaunchKernelGGL(k_scan_exclusive<uint64_t>, dim3(1), dim3(kScanThreads), 0, st, fl, pre, (int64_t)m,
+                                   tot64);
+                hipLaunchKernelGGL(k_ploc_merge, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl, pre,
+                                   node_base, cid, clo, chi, cid2, clo2, chi2, left, right, cnt, nlo, nhi);
+                uint64_t t = 0;
+                VF_HIP(hipMemcpyAsync(&t, tot64, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+                VF_HIP(hipStreamSynchronize(st));
+                const int32_t merges = (int32_t)(t & 0xffffffffu), kept = (int32_t)(t >> 32);
+                // the best pair is always mutual; anything else means corrupted input
+                if (merges <= 0 || kept != m - merges || node_base + merges > nt - 1)
+                    return fail(VF_EHIP, "scene build: clustering pass made no progress");
+                pass_base.push_back(node_base);
+                node_base += merges;
+                m = kept;
+                std::swap(cid, cid2);
+                std::swap(clo, clo2);
+                std::swap(chi, chi2);
+            }
+            pass_base.push_back(node_base);   // == nt - 1
+            const int32_t root = nt - 2;
+            VF_HIP(hipMemsetAsync(off + root, 0, sizeof(int32_t), st));
+            for (int p = (int)pass_base.size() - 2; p >= 0; --p) {
+                const int32_t k0 = pass_base[p], k1 = pass_base[p + 1];
+                hipLaunchKernelGGL(k_ploc_offsets, dim3(blocks_for(k1 - k0, 256)), dim3(256), 0, st, k0, k1, left,
+                                   right, cnt, off, newpos);
+            }
+            hipLaunchKernelGGL(k_ploc_finish, dim3(blocks_for(nt, 256)), dim3(256), 0, st, nt, left, right, cnt, off,
+                               newpos, first, last, vals, dfs_vals);
+            leaf_vals = dfs_vals;
+            if ((s = collapse(root, leaf_vals, &too_deep)) != VF_OK) return s;
         }
-        n_nodes = base;
-        for (int L = depth - 1; L >= 0; --L)
-            hipLaunchKernelGGL(k_bounds, dim3(blocks_for(level_n[L], 128)), dim3(128), 0, st, tmp_nodes,
-                               level_base[L], level_n[L], va == vals ? vals : va, tlo, thi);
+        if (too_deep) {
+            // the Morton radix tree (its depth is bounded by the key bits plus log2 of duplicates)
+            hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, ka, nt, left, right,
+                               first, last);
+            hipLaunchKernelGGL(k_parents, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, left, right, nt, par_int,
+                               par_leaf);
+            VF_HIP(hipMemsetAsync(flags, 0, (size_t)nt * 4, st));
+            hipLaunchKernelGGL(k_binary_bounds, dim3(blocks_for(nt, 256)), dim3(256), 0, st, left, right, nt, vals,
+                               tlo, thi, par_int, par_leaf, flags, nlo, nhi);
+            leaf_vals = vals;
+            if ((s = collapse(0, leaf_vals, &too_deep)) != VF_OK) return s;
+            if (too_deep) return fail(VF_EINVAL, "scene BVH deeper than the traversal stack allows");
+        }
     }
     node_bytes = (int64_t)n_nodes * (int64_t)sizeof(Node);
     int64_t total_bytes = node_bytes + tri_bytes + map_bytes + rgb_bytes;
@@ -694,7 +890,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     if (e == hipSuccess)
         e = hipMemsetAsync((char*)tri_out + (int64_t)nt * sizeof(Tri), 0, kLeafMax * sizeof(Tri), st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_tri_write, dim3(blocks_for(nt, 256)), dim3(256), 0, st, verts, tris, va, nt, nv, tri_out,
+        hipLaunchKernelGGL(k_tri_write, dim3(blocks_for(nt, 256)), dim3(256), 0, st, verts, tris, leaf_vals, nt, nv, tri_out,
                            sorted_of);
         if (rgb)
             e = hipMemcpyAsync(rgb_out, rgb, (size_t)nt * 3, hipMemcpyDeviceToDevice, st);

@@ -32,6 +32,10 @@ constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 #define VF_LEAF_MAX 4
 #endif
 constexpr int kLeafMax = VF_LEAF_MAX;  // triangles per BVH leaf (at most 8: the stack entry keeps 3 bits)
+#ifndef VF_BVH_PLOC
+#define VF_BVH_PLOC 1
+#endif
+constexpr bool kBvhPloc = VF_BVH_PLOC != 0;  // binary tree by PLOC (else the Morton radix tree)
 #ifndef VF_BVH_WIDTH
 #define VF_BVH_WIDTH 4
 #endif
