@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 latency"
 # VALU lane-operations per test as issued by the traversal kernel:
 OPS_PER_BOX = 18       # 6 fused slab distances, 10 min/max, 1 mul (exit growth), 1 compare
+OPS_PER_BOX_OCT = 11   # one-octant packet: 6 fused slab distances (exit growth folded in), 4 min/max, 1 compare
 OPS_PER_TRI = 42       # Moller-Trumbore: 2 cross products, 4 dots, 3 subs, rcp, 3 muls, 1 add, 8 compares, 2 selects
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
 HBM_PEAK_GBPS = 8000.0
@@ -382,7 +383,8 @@ def main():
         st = ctx.read_stats(reset=True)
         box = st["box_lane"] / args.steps
         tri = st["tri_lane"] / args.steps
-        ops = box * OPS_PER_BOX + tri * OPS_PER_TRI
+        box_oct = st["box_lane_octant"] / args.steps
+        ops = box_oct * OPS_PER_BOX_OCT + (box - box_oct) * OPS_PER_BOX + tri * OPS_PER_TRI
         achieved = ops / render_s / 1e12
         rays = st["rays"] / args.steps
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
@@ -390,6 +392,7 @@ def main():
                            "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
                                           "wave_node_visits": st["node_wave"] / args.steps,
                                           "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
+                                          "one_octant_box_fraction": box_oct / max(box, 1),
                                           "valu_ops": ops}}
         out["ray_tri_tests_per_s"] = tri / (ms_per_step / 1e3)
         out["rays_per_s"] = rays / (ms_per_step / 1e3)

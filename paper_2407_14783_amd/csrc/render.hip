@@ -53,10 +53,13 @@ __device__ __forceinline__ float safe_inv(float x) {
 }
 
 struct TraceStats {
-    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits;
+    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_oct;
 };
 
-template <int NR, bool STATS>
+// OCT >= 0: every ray of the packet has the direction octant OCT (bit set = negative component, by
+// the sign bit, as the reciprocal takes it), so the near and far planes of each slab are known at
+// compile time; OCT < 0: rays of several octants, both planes tested per axis.
+template <int NR, bool STATS, int OCT>
 __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&valid)[NR], const float o[3],
                                              const float (&d)[NR][3], float t_near, float t_far,
                                              float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
@@ -87,8 +90,20 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
     float tb_box[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) tb_box[r] = t_best[r] * unshrink;
-    int oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
-    oct = uniform_i(oct);
+    // far-plane distances of a known-octant packet come out grown: (x - o) (1/d) grow2 as one fused
+    // multiply-add of the products rounded once more (a relative 2^-24 each, far inside the padding)
+    float ing[NR][3], oig[NR][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        for (int k = 0; k < 3; ++k) {
+            ing[r][k] = inv[r][k] * grow2;
+            oig[r][k] = oi[r][k] * grow2;
+        }
+    int oct = OCT;
+    if constexpr (OCT < 0) {
+        oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
+        oct = uniform_i(oct);
+    }
     if (__ballot(any) == 0ull) return;
 
     int stk0 = 0, stk1 = 0;
@@ -105,6 +120,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             // them keeps the node one run of 16-dword loads
             if constexpr (kWidth == 4) {
                 asm volatile("" ::"s"(w[28]), "s"(w[31]));
+                if constexpr (OCT >= 0) asm volatile("" ::"s"(w[29]), "s"(w[30]));
             } else {
 #pragma unroll
                 for (int i = kOrderWord; i < kNodeWords; ++i) asm volatile("" ::"s"(w[i]));
@@ -113,6 +129,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 ts.node_wave += 1;
                 ts.node_lane += n_valid;
                 ts.box_lane += kWidth * n_valid;
+                if (OCT >= 0) ts.box_oct += kWidth * n_valid;
             }
             // bit k: some ray of the packet enters child k's box (empty slots hold a box no ray enters)
             uint32_t hb = 0;
@@ -122,6 +139,20 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 const float loy = __uint_as_float(w[2 * kWidth + k]), hiy = __uint_as_float(w[3 * kWidth + k]);
                 const float loz = __uint_as_float(w[4 * kWidth + k]), hiz = __uint_as_float(w[5 * kWidth + k]);
                 uint64_t m = 0;   // lanes with a ray entering the box (the union over the lane's rays)
+                if constexpr (OCT >= 0) {
+                    const float nx = (OCT & 1) ? hix : lox, fx = (OCT & 1) ? lox : hix;
+                    const float ny = (OCT & 2) ? hiy : loy, fy = (OCT & 2) ? loy : hiy;
+                    const float nz = (OCT & 4) ? hiz : loz, fz = (OCT & 4) ? loz : hiz;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float tnx = fmaf(nx, inv[r][0], oi[r][0]), tfx = fmaf(fx, ing[r][0], oig[r][0]);
+                        const float tny = fmaf(ny, inv[r][1], oi[r][1]), tfy = fmaf(fy, ing[r][1], oig[r][1]);
+                        const float tnz = fmaf(nz, inv[r][2], oi[r][2]), tfz = fmaf(fz, ing[r][2], oig[r][2]);
+                        const float t0 = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, t_near));
+                        const float t1 = fminf(fminf(tfx, tfy), fminf(tfz, tb_box[r]));
+                        m |= __ballot(t0 <= t1);
+                    }
+                } else
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     // (lo - o) / d as one fused multiply-add: lo * (1/d) - o * (1/d)
@@ -296,7 +327,7 @@ __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) 
 }
 
 template <bool FUSED, bool STATS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
 k_render(RenderArgs a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
@@ -364,8 +395,36 @@ k_render(RenderArgs a) {
     for (int k = 0; k < NR; ++k) pixel_ray(rot, tan_h, vw.H, vw.W, row[k], col[k], d[k]);
     float t_best[NR];
     int32_t id_best[NR];
-    TraceStats ts = {0, 0, 0, 0, 0, 0};
-    trace_packet<NR, STATS>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts);
+    TraceStats ts = {0, 0, 0, 0, 0, 0, 0};
+    // one octant for every ray of the packet (lanes outside the image do not count: their best depth
+    // of -1 fails every test)?  Then the traversal with the slab planes fixed at compile time.
+    uint64_t m_neg[3] = {0, 0, 0}, m_pos[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            m_neg[c] |= __ballot(valid[k] && signbit(d[k][c]));
+            m_pos[c] |= __ballot(valid[k] && !signbit(d[k][c]));
+        }
+    const bool one_oct = (m_neg[0] == 0 || m_pos[0] == 0) && (m_neg[1] == 0 || m_pos[1] == 0) &&
+                         (m_neg[2] == 0 || m_pos[2] == 0);
+    const int pk_oct = (m_neg[0] ? 1 : 0) | (m_neg[1] ? 2 : 0) | (m_neg[2] ? 4 : 0);
+#define VF_TRACE(O) trace_packet<NR, STATS, O>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts)
+    if (!VF_OCTANT_PACKETS || !one_oct) {
+        VF_TRACE(-1);
+    } else {
+        switch (pk_oct) {
+            case 0: VF_TRACE(0); break;
+            case 1: VF_TRACE(1); break;
+            case 2: VF_TRACE(2); break;
+            case 3: VF_TRACE(3); break;
+            case 4: VF_TRACE(4); break;
+            case 5: VF_TRACE(5); break;
+            case 6: VF_TRACE(6); break;
+            default: VF_TRACE(7); break;
+        }
+    }
+#undef VF_TRACE
     if (vw.swarm != 0) trace_members<NR>(a, vw, slot, sc.n_tris, valid, o, d, t_best, id_best);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -394,11 +453,12 @@ k_render(RenderArgs a) {
     }
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
-        unsigned long long v[6] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits};
+        unsigned long long v[7] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
+                                   ts.box_oct};
         unsigned long long rays = 0;
         for (int k = 0; k < NR; ++k) rays += valid[k] ? 1 : 0;
         for (int off = 32; off > 0; off >>= 1) {
-            for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], off);
+            for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], off);
             rays += __shfl_xor(rays, off);
         }
         if (lane == 0) {
@@ -408,7 +468,7 @@ k_render(RenderArgs a) {
             atomicAdd(&a.stats[3], v[2]);
             atomicAdd(&a.stats[4], v[3] / 64);   // wave-level counts were added by every lane
             atomicAdd(&a.stats[5], v[4] / 64);
-            atomicAdd(&a.stats[6], v[1]);
+            atomicAdd(&a.stats[6], v[6]);
             atomicAdd(&a.stats[7], v[5]);
         }
     }
@@ -543,7 +603,7 @@ hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st) {
     int64_t total = (int64_t)a.n * a.groups_per_agent;
     if (total > 0x7fffffff) return hipErrorInvalidValue;
     a.total_groups = (int32_t)total;
-    dim3 grid((unsigned)total), block(256);
+    dim3 grid((unsigned)total), block(64 * kWavesPerBlock);
     if (fused) {
         if (stats)
             hipLaunchKernelGGL((k_render<true, true>), grid, block, 0, st, a);

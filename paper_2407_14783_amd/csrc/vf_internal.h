@@ -19,7 +19,13 @@ namespace vf {
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
-constexpr int kWavesPerBlock = 4;     // render workgroup = 4 wavefronts = 4 packets
+#ifndef VF_OCTANT_PACKETS
+#define VF_OCTANT_PACKETS 1   // packets of one ray octant take the traversal with fixed slab planes
+#endif
+#ifndef VF_RENDER_WAVES
+#define VF_RENDER_WAVES 1
+#endif
+constexpr int kWavesPerBlock = VF_RENDER_WAVES;  // render workgroup = this many wavefronts, one packet each
 #ifndef VF_PACKET_ROWS
 #define VF_PACKET_ROWS 1
 #endif
