@@ -127,6 +127,8 @@ typedef struct vf_scene_info {
     float bounds_hi[3];
     float build_ms;       /* device time of the build (ms) */
     int32_t width;        /* children per node: 4 (vf_bvh4_node) or 8 (vf_bvh8_node) */
+    int32_t builder;      /* binary tree the BVH was collapsed from: VF_BVH_CLUSTER or VF_BVH_RADIX */
+    int32_t reserved;
 } vf_scene_info;
 
 /* BVH node as stored in HBM (for vf_scene_export); vf_scene_info.width says which
@@ -326,6 +328,16 @@ vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
  * the render grid has at most 1,024 workgroups (16 agents at 64x64), else split. */
 enum { VF_LAUNCH_SPLIT = 0, VF_LAUNCH_FUSED = 1, VF_LAUNCH_AUTO = 2 };
 vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode);
+
+/* Binary tree that later scene builds collapse into the wide BVH.
+ * VF_BVH_CLUSTER (the default): locally-ordered clustering (PLOC, Meister and
+ * Bittner 2018) of the triangles in Morton order, radius 6.  VF_BVH_RADIX: the
+ * Morton radix tree (Karras 2012), about half the build time.  A clustered tree
+ * too deep for the traversal stack is replaced by the radix tree;
+ * vf_scene_info.builder reports which one a scene got.  Both give identical
+ * images (up to exact depth ties, broken by the lower triangle id either way). */
+enum { VF_BVH_CLUSTER = 0, VF_BVH_RADIX = 1 };
+vf_status vf_set_bvh_builder(vf_ctx* ctx, int32_t builder);
 
 /* Enable (1) / disable (0) traversal statistics: while enabled, vf_step and
  * vf_render use a counting variant of the render kernel that accumulates node

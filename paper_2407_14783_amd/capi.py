@@ -16,6 +16,7 @@ VF_OK, VF_EINVAL, VF_ENOMEM, VF_ENOSCENE, VF_EHIP, VF_EBUSY, VF_EDEVICE = 0, -1,
 VF_RK4, VF_EULER = 0, 1
 VF_CTBR, VF_SRT, VF_PS, VF_LV = 0, 1, 2, 3
 VF_LAUNCH_SPLIT, VF_LAUNCH_FUSED, VF_LAUNCH_AUTO = 0, 1, 2
+VF_BVH_CLUSTER, VF_BVH_RADIX = 0, 1
 VF_NOISE_NONE, VF_NOISE_NORMAL, VF_NOISE_SPECKLE, VF_NOISE_SALT_PEPPER = 0, 1, 2, 3
 STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE", -4: "VF_EHIP", -5: "VF_EBUSY",
                 -6: "VF_EDEVICE"}
@@ -23,7 +24,7 @@ STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE",
 # every symbol include/visfly.h declares
 EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_scene_info_get", "vf_scene_export",
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
-            "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_server_create",
+            "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_set_bvh_builder", "vf_server_create",
             "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
             "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_timing", "vf_timing_read")
 
@@ -47,7 +48,7 @@ class SceneInfo(ctypes.Structure):
     _fields_ = [("n_tris", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("depth", ctypes.c_int32), ("leaf_max", ctypes.c_int32),
                 ("bounds_lo", ctypes.c_float * 3), ("bounds_hi", ctypes.c_float * 3), ("build_ms", ctypes.c_float),
-                ("width", ctypes.c_int32)]
+                ("width", ctypes.c_int32), ("builder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 VIEW_DTYPE = np.dtype([("scene_id", "<i4"), ("H", "<i4"), ("W", "<i4"), ("flags", "<i4"), ("hfov", "<f4"),
@@ -90,6 +91,7 @@ def _load():
         "vf_render_backward": ([P, I64, P, P, I32, I32, P, P, I64, P, P], I32),
         "vf_set_stats": ([P, I32], I32),
         "vf_set_launch_mode": ([P, I32], I32),
+        "vf_set_bvh_builder": ([P, I32], I32),
         "vf_set_spatial_order": ([P, I32], I32),
         "vf_set_timing": ([P, I32], I32),
         "vf_timing_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32], I32),

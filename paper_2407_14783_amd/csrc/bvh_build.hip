@@ -772,6 +772,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     // triangle of each leaf position: Morton order, or depth-first order of the clustered tree
     const uint32_t* leaf_vals = vals;
     uint32_t* dfs_vals = nullptr;
+    int32_t builder_used = ctx->bvh_builder;
     int32_t n_nodes = 0;
     bool single_leaf = nt <= kLeafMax;
     if (single_leaf) {
@@ -817,7 +818,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
             return VF_OK;
         };
         bool too_deep = true;
-        if (kBvhPloc) {
+        if (ctx->bvh_builder == VF_BVH_CLUSTER) {
             int32_t *cid, *cid2, *nn, *cnt, *off, *newpos;
             float4 *clo, *chi, *clo2, *chi2;
             uint64_t *fl, *pre, *tot64;
@@ -865,6 +866,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
             if ((s = collapse(root, leaf_vals, &too_deep)) != VF_OK) return s;
         }
         if (too_deep) {
+            builder_used = VF_BVH_RADIX;
             // the Morton radix tree (its depth is bounded by the key bits plus log2 of duplicates)
             hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(nt - 1, 256)), dim3(256), 0, st, ka, nt, left, right,
                                first, last);
@@ -928,6 +930,8 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     }
     out->info.build_ms = ms;
     out->info.width = kWidth;
+    out->info.builder = builder_used;
+    out->info.reserved = 0;
     out->desc.nodes = nodes;
     out->desc.tris = tri_out;
     out->desc.rgb = rgb_out;

@@ -646,6 +646,13 @@ vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode) {
     return VF_OK;
 }
 
+vf_status vf_set_bvh_builder(vf_ctx* ctx, int32_t builder) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_bvh_builder: NULL context");
+    if (builder != VF_BVH_CLUSTER && builder != VF_BVH_RADIX) return fail(VF_EINVAL, "vf_set_bvh_builder: bad builder");
+    ctx->bvh_builder = builder;
+    return VF_OK;
+}
+
 vf_status vf_set_stats(vf_ctx* ctx, int32_t enable) {
     if (!ctx) return fail(VF_EINVAL, "vf_set_stats: NULL context");
     ctx->stats = enable != 0;

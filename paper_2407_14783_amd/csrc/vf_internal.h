@@ -38,10 +38,6 @@ constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 #define VF_LEAF_MAX 4
 #endif
 constexpr int kLeafMax = VF_LEAF_MAX;  // triangles per BVH leaf (at most 8: the stack entry keeps 3 bits)
-#ifndef VF_BVH_PLOC
-#define VF_BVH_PLOC 1
-#endif
-constexpr bool kBvhPloc = VF_BVH_PLOC != 0;  // binary tree by PLOC (else the Morton radix tree)
 #ifndef VF_BVH_WIDTH
 #define VF_BVH_WIDTH 4
 #endif
@@ -122,6 +118,7 @@ struct alignas(16) SceneDesc {
     int32_t pad[4];
 };
 static_assert(sizeof(SceneDesc) == 64, "scene table entry is 64 bytes");
+static_assert(sizeof(vf_scene_info) == 80, "vf_scene_info layout");
 static_assert(sizeof(vf_view) == 72, "view descriptor is 72 bytes");
 static_assert(sizeof(vf_dyn_params) == 128, "parameter block is 128 bytes");
 static_assert(sizeof(vf_noise) == 32, "noise block is 32 bytes");
@@ -190,6 +187,7 @@ struct vf_ctx {
     unsigned long long* d_stats = nullptr; // 8 counters
     bool stats = false;
     int32_t launch_mode = VF_LAUNCH_AUTO;
+    int32_t bvh_builder = VF_BVH_CLUSTER;
     std::vector<vf::Counters> counters;
     vf::SwarmTable swarm{};                // device copy of the swarm lists (n = 0: none)
     int64_t swarm_bytes = 0;

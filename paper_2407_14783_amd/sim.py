@@ -104,7 +104,8 @@ class Context:
         check(lib.vf_scene_info_get(self.h, sid, ctypes.byref(info)), "vf_scene_info_get")
         return {"n_tris": info.n_tris, "n_nodes": info.n_nodes, "bytes": info.bytes, "depth": info.depth,
                 "leaf_max": info.leaf_max, "bounds_lo": list(info.bounds_lo), "bounds_hi": list(info.bounds_hi),
-                "build_ms": info.build_ms, "width": info.width}
+                "build_ms": info.build_ms, "width": info.width,
+                "builder": "cluster" if info.builder == capi.VF_BVH_CLUSTER else "radix"}
 
     def export_scene(self, sid):
         info = self.scene_info(sid)
@@ -259,6 +260,12 @@ class Context:
         """True: fused single launch; False: split; None: automatic by batch size (the default)."""
         mode = capi.VF_LAUNCH_AUTO if fused is None else (capi.VF_LAUNCH_FUSED if fused else capi.VF_LAUNCH_SPLIT)
         check(lib.vf_set_launch_mode(self.h, mode), "vf_set_launch_mode")
+
+    def set_bvh_builder(self, builder):
+        """Binary tree of later scene builds: "cluster" (locally-ordered clustering, the default) or "radix"
+        (the Morton radix tree)."""
+        code = {"cluster": capi.VF_BVH_CLUSTER, "radix": capi.VF_BVH_RADIX}[builder]
+        check(lib.vf_set_bvh_builder(self.h, code), "vf_set_bvh_builder")
 
     def set_spatial_order(self, on):
         """Sort split-launch batches by (scene, position) before rendering (default on)."""

@@ -39,6 +39,7 @@ def test_struct_layouts_match_header():
     assert capi.NODE_DTYPE.itemsize == 128 and capi.TRI_DTYPE.itemsize == 48
     assert capi.NODE_DTYPE.fields["child"][1] == 96 and capi.NODE_DTYPE.fields["count"][1] == 112
     assert capi.NODE_DTYPE.fields["order"][1] == 116
+    assert ctypes.sizeof(capi.SceneInfo) == 80 and capi.SceneInfo.builder.offset == 72
     assert capi.NODE8_DTYPE.itemsize == 256 and capi.NODE8_DTYPE.fields["child"][1] == 192
     assert capi.NODE8_DTYPE.fields["order"][1] == 224
 

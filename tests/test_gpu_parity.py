@@ -454,10 +454,8 @@ def test_spatial_order_changes_nothing(vf):
 # BVH invariants
 # ---------------------------------------------------------------------------
 
-def test_bvh_invariants_and_deterministic_rebuild(vf):
-    sim, ctx = vf
-    sc = scenes.forest(seed=3, n_trees=500)
-    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+def _check_bvh(ctx, sid, sc):
+    """Structural invariants of a built scene; returns the exported (nodes, tris)."""
     nodes, tris = ctx.export_scene(sid)
     info = ctx.scene_info(sid)
     T = sc["tris"].shape[0]
@@ -504,11 +502,94 @@ def test_bvh_invariants_and_deterministic_rebuild(vf):
     valid0 = nodes["child"][0] != empty
     assert np.all(lo[0][valid0].min(0) <= v.min(0)) and np.all(hi[0][valid0].max(0) >= v.max(0))
     assert info["depth"] >= 2 and info["n_nodes"] == len(nodes)
+    return nodes, tris
+
+
+def test_bvh_invariants_and_deterministic_rebuild(vf):
+    sim, ctx = vf
+    sc = scenes.forest(seed=3, n_trees=500)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    nodes, tris = _check_bvh(ctx, sid, sc)
+    assert ctx.scene_info(sid)["builder"] == "cluster"
     sid2 = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
     nodes2, tris2 = ctx.export_scene(sid2)
     assert nodes.tobytes() == nodes2.tobytes() and tris.tobytes() == tris2.tobytes()
     ctx.free_scene(sid)
     ctx.free_scene(sid2)
+
+
+def test_bvh_builders_agree(vf):
+    """The clustered and the radix-tree BVH of the same scene: both valid, and the same images bit for bit
+    (the closest hit does not depend on the tree; ties go to the lower id either way)."""
+    sim, ctx = vf
+    p = default_params()
+    outs = {}
+    for name, sc in (("forest", scenes.forest(seed=3, n_trees=500)), ("room graph", scenes.room_graph(7, 20000))):
+        if name == "forest":
+            states = agents.forest_starts(4, 6, sc, p)
+        else:
+            states = agents.room_graph_starts(8, 6, sc, p)
+        for builder in ("radix", "cluster"):
+            ctx.set_bvh_builder(builder)
+            sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+            assert ctx.scene_info(sid)["builder"] == builder
+            header(f"BVH builders: {name}, {builder} tree")
+            _check_bvh(ctx, sid, sc)
+            outs[(name, builder)] = _render(ctx, sim, sid, states)
+            ctx.free_scene(sid)
+        for a, b in zip(outs[(name, "radix")][:3], outs[(name, "cluster")][:3]):
+            assert np.array_equal(a, b), f"{name}: images differ between the two trees"
+        fr = _check_agents(sc, states[:2], *outs[(name, "cluster")], (64, 64), label=f"{name} cluster")
+        assert np.mean(fr) < 0.02
+    ctx.set_bvh_builder("cluster")
+
+
+def _look_quat(f):
+    """Attitude whose body x axis (the camera axis) points along f, with no roll."""
+    f = np.asarray(f, dtype=np.float64) / np.linalg.norm(f)
+    yaw, el = math.atan2(f[1], f[0]), math.asin(f[2])
+    qz = np.array([math.cos(yaw / 2), 0.0, 0.0, math.sin(yaw / 2)])
+    qy = np.array([math.cos(-el / 2), 0.0, math.sin(-el / 2), 0.0])
+    w1, x1, y1, z1 = qz
+    w2, x2, y2, z2 = qy
+    q = np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                  w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+    assert np.allclose(oren.quat_to_rot(q)[:, 0], f, atol=1e-12)
+    return q
+
+
+def test_octant_packets_all_eight_and_mixed(vf):
+    """Narrow views along the eight octant diagonals put every ray of every packet in one octant (the
+    traversal with fixed slab planes); wide views across the horizon mix octants in a packet.  Both kinds
+    against the oracle, and the counting variant shows which traversal ran."""
+    sim, ctx = vf
+    p = default_params()
+    sc = scenes.box_room(seed=1)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    dirs = [(sx, sy, sz) for sz in (1, -1) for sy in (1, -1) for sx in (1, -1)]
+    q = np.stack([_look_quat(f) for f in dirs])
+    states = agents.make_states(np.tile([5.0, 5.0, 2.0], (8, 1)), p, quat=q)
+    header("octant packets: 8 narrow views along the octant diagonals, 32x32")
+    ctx.read_stats(reset=True)
+    ctx.set_stats(True)
+    depth, ids, rgb, offs = _render(ctx, sim, sid, states, hw=(32, 32), hfov=0.3)
+    ctx.set_stats(False)
+    st = ctx.read_stats(reset=True)
+    assert st["box_lane"] > 0 and st["box_lane_octant"] == st["box_lane"]
+    fr = _check_agents(sc, states, depth, ids, rgb, offs, (32, 32), hfov=0.3, label="octant view")
+    assert np.mean(fr) < 0.02
+    # wide views level with the horizon: the rows of tiles across it hold rays of both vertical signs
+    q2 = np.stack([_look_quat(f) for f in ((1, 0.3, 0), (-0.4, -1, 0), (0.2, 1, 0.05))])
+    states2 = agents.make_states(np.tile([5.0, 5.0, 2.0], (3, 1)), p, quat=q2)
+    header("octant packets: 3 wide views across the horizon, 64x64 (mixed packets)")
+    ctx.set_stats(True)
+    depth, ids, rgb, offs = _render(ctx, sim, sid, states2, hw=(64, 64), hfov=2.0)
+    ctx.set_stats(False)
+    st = ctx.read_stats(reset=True)
+    assert 0 < st["box_lane_octant"] < st["box_lane"]
+    fr = _check_agents(sc, states2, depth, ids, rgb, offs, (64, 64), hfov=2.0, label="mixed view")
+    assert np.mean(fr) < 0.02
+    ctx.free_scene(sid)
 
 
 # ---------------------------------------------------------------------------
