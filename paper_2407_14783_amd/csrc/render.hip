@@ -245,7 +245,9 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     float t = tq * inv_det;
                     // bitwise, not short-circuit: no divergent branches.  An empty best (id -1) compares
                     // as the largest unsigned id, so any hit at the same depth replaces it.
-                    const bool h = (det != 0.0f) & (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t >= t_near);
+                    // det == 0 needs no test of its own: 1/det is infinite, so u and v are infinite or
+                    // NaN and one of the comparisons fails
+                    const bool h = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t >= t_near);
                     const bool take = h & ((t < t_best[r]) | ((t == t_best[r]) & ((uint32_t)id < (uint32_t)id_best[r])));
                     t_best[r] = take ? t : t_best[r];
                     id_best[r] = take ? id : id_best[r];
