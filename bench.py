@@ -32,7 +32,9 @@ METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 l
 # VALU lane-operations per test as issued by the traversal kernel:
 OPS_PER_BOX = 18       # 6 fused slab distances, 10 min/max, 1 mul (exit growth), 1 compare
 OPS_PER_BOX_OCT = 11   # one-octant packet: 6 fused slab distances (exit growth folded in), 4 min/max, 1 compare
-OPS_PER_TRI = 42       # Moller-Trumbore: 2 cross products, 4 dots, 3 subs, rcp, 3 muls, 1 add, 8 compares, 2 selects
+NODE_BYTES, TRI_BYTES = 128, 48   # one 4-wide node; one leaf triangle record
+OPS_PER_TRI = 42       # Moller-Trumbore as compiled: 28 mul/FMA (2 cross, 4 dot, 3 scalings by 1/det, u+v), 3 subs,
+                       # 1 reciprocal, 7 compares, 2 selects, 1 move
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
 HBM_PEAK_GBPS = 8000.0
 
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--multi-scene-only", action="store_true",
+                    help="run only the multi-scene batch and print its record (for counter runs)")
     ap.add_argument("--no-spatial-order", action="store_true",
                     help="render agents in the given order instead of (scene, position) order")
     return ap.parse_args()
@@ -73,12 +77,12 @@ def copy_calibration():
 TRAFFIC_SOURCES = ("render.hip", "vf_internal.h", "dynamics.h", "bvh_build.hip")
 
 
-def committed_traffic():
-    """(fetch_kib, write_kib) per dispatch from profiles/render_forest256_pmc.md if the render kernel's
+def committed_traffic(name="render_forest256_pmc.md"):
+    """(fetch_kib, write_kib) per dispatch from a profiles/ counter summary if the render kernel's
     sources and the BVH build (which lays out what it reads) still hash as when the counters were taken,
     else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "render_forest256_pmc.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     line = [l for l in open(path) if l.startswith("traffic_kib_per_dispatch:")]
@@ -114,8 +118,19 @@ def cpu_baseline(sc, s0, acts, params, budget_s):
             break
     dt = time.perf_counter() - t0
     return {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
             "sample": f"{n_agents} agents x {k} steps of the forest-256 workload (FP64 RK4 + brute-force "
                       f"all-triangle ray casting, {frames} frames, {dt:.1f} s)"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline_extra(params):
@@ -234,22 +249,54 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
         ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    ctx.set_timing(True)
     e0.record()
     for k in range(steps):
         ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
     e1.record()
     torch.cuda.synchronize()
     ctx.sync_check()
+    render_ms, render_launches = ctx.timing_read(reset=True)
+    ctx.set_timing(False)
+    render_s = render_ms / 1e3 / max(render_launches, 1)
     ms = e0.elapsed_time(e1) / steps
     infos = [ctx.scene_info(s) for s in sids]
     for s in sids:
         ctx.free_scene(s)
-    return {"workload": "multi-scene: 4,096 agents over 8 room graphs (20k-2M triangles), half 64x64 half 128x128",
-            "ms_per_step": ms, "frames_per_s": 4096 / (ms / 1e3), "rays_per_s": npx / (ms / 1e3),
-            "frames_64x64_equivalent_per_s": npx / 4096 / (ms / 1e3),
-            "scene_triangles": [int(i["n_tris"]) for i in infos],
-            "scene_build_device_ms": [round(float(i["build_ms"]), 2) for i in infos],
-            "scene_build_wall_s_incl_upload": build_s}
+    out = {"workload": "multi-scene: 4,096 agents over 8 room graphs (20k-2M triangles), half 64x64 half 128x128",
+           "ms_per_step": ms, "frames_per_s": 4096 / (ms / 1e3), "rays_per_s": npx / (ms / 1e3),
+           "frames_64x64_equivalent_per_s": npx / 4096 / (ms / 1e3),
+           "render_kernel_avg_us": render_s * 1e6,
+           "scene_triangles": [int(i["n_tris"]) for i in infos],
+           "scene_bytes": [int(i["bytes"]) for i in infos],
+           "scene_build_device_ms": [round(float(i["build_ms"]), 2) for i in infos],
+           "scene_build_wall_s_incl_upload": build_s}
+    tk = committed_traffic("render_multiscene4096_pmc.md")
+    if tk:
+        traffic = (tk[0] + tk[1]) * 1024.0
+        out["hbm"] = {"bytes_per_launch": traffic, "achieved_GBps": traffic / render_s / 1e9,
+                      "peak_GBps": HBM_PEAK_GBPS, "frac": traffic / render_s / 1e9 / HBM_PEAK_GBPS,
+                      "source": "profiles/render_multiscene4096_pmc.md"}
+    return out
+
+
+def copy_ceiling_gbps(reps=5):
+    """Measured HBM ceiling: a plain 1 GiB device-to-device copy (read + write bytes per second)."""
+    import torch
+    a = torch.empty(256 * 2 ** 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def bptt_throughput(ctx, sim, params, n=1024, horizon=64, k=8):
@@ -298,6 +345,12 @@ def main():
         return
     import torch
     from paper_2407_14783_amd import sim
+    if args.multi_scene_only:
+        from workloads import default_params
+        ctx = sim.Context(0)
+        print(json.dumps({"multi_scene": multi_scene_throughput(ctx, sim, default_params())}))
+        ctx.close()
+        return
     from workloads import agents, default_params, scenes
 
     params = default_params()
@@ -387,13 +440,20 @@ def main():
         ops = box_oct * OPS_PER_BOX_OCT + (box - box_oct) * OPS_PER_BOX + tri * OPS_PER_TRI
         achieved = ops / render_s / 1e12
         rays = st["rays"] / args.steps
+        box_ops = (box_oct * OPS_PER_BOX_OCT + (box - box_oct) * OPS_PER_BOX) / max(box, 1)
+        logical = st["node_wave"] / args.steps * NODE_BYTES + st["tri_wave"] / args.steps * TRI_BYTES
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
                            "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                            "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
                                           "wave_node_visits": st["node_wave"] / args.steps,
                                           "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
                                           "one_octant_box_fraction": box_oct / max(box, 1),
-                                          "valu_ops": ops}}
+                                          "valu_ops": ops, "logical_scene_bytes": logical}}
+        out["test_rates"] = {"ray_box_tests_per_s": box / render_s, "ray_tri_tests_per_s": tri / render_s,
+                             "valu_ceiling_box_tests_per_s": ALU_PEAK_TOPS * 1e12 / box_ops,
+                             "valu_ceiling_tri_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_TRI,
+                             "logical_scene_GBps": logical / render_s / 1e9,
+                             "basis": "per second of render-kernel time; ceilings = VALU peak / ops per test"}
         out["ray_tri_tests_per_s"] = tri / (ms_per_step / 1e3)
         out["rays_per_s"] = rays / (ms_per_step / 1e3)
     tk = tuple(float(x) for x in args.traffic_kib.split(",")) if args.traffic_kib else committed_traffic()
@@ -404,6 +464,10 @@ def main():
             out["roofline"]["traffic"] = traffic
         out["hbm"] = {"bytes_per_launch": traffic, "achieved_GBps": traffic / render_s / 1e9,
                       "peak_GBps": HBM_PEAK_GBPS, "frac": traffic / render_s / 1e9 / HBM_PEAK_GBPS}
+        if not args.no_extra:
+            cc = copy_ceiling_gbps()
+            out["hbm"]["copy_ceiling_GBps"] = cc
+            out["hbm"]["frac_of_copy"] = traffic / render_s / 1e9 / cc
     if not args.no_serving:
         out["serving"] = serving_summary(ctx, sim, params)
     if not args.no_extra:
