@@ -167,6 +167,52 @@ __global__ void k_scan_exclusive(const T* __restrict__ in, T* __restrict__ out, 
     if (threadIdx.x == kScanThreads - 1 && total) *total = sums[kScanThreads - 1];
 }
 
+// Multi-workgroup exclusive scan for long arrays: the sum of each tile of kScanTile elements, an
+// exclusive scan of the tile sums (one workgroup), then each tile scanned with its offset.
+constexpr int kScanTile = 4 * kScanThreads;
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_tile_sums(const T* __restrict__ in, int64_t n, T* __restrict__ sums) {
+    __shared__ T red[kScanThreads];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * (int64_t)threadIdx.x;
+    T v = 0;
+    for (int j = 0; j < 4; ++j)
+        if (i0 + j < n) v += in[i0 + j];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan(const T* __restrict__ in, int64_t n,
+                                                             const T* __restrict__ tile_off, T* __restrict__ out) {
+    __shared__ T sums[kScanThreads];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * (int64_t)threadIdx.x;
+    T v[4];
+    T s = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = i0 + j < n ? in[i0 + j] : (T)0;
+        s += v[j];
+    }
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {   // Hillis-Steele inclusive scan of the thread sums
+        T u = (int)threadIdx.x >= off ? sums[threadIdx.x - off] : (T)0;
+        __syncthreads();
+        sums[threadIdx.x] += u;
+        __syncthreads();
+    }
+    T run = tile_off[blockIdx.x] + (threadIdx.x > 0 ? sums[threadIdx.x - 1] : (T)0);
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < n) out[i0 + j] = run;
+        run += v[j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of (key, value) pairs, 8-bit digits
 // ---------------------------------------------------------------------------
@@ -686,6 +732,20 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
 
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
+// Exclusive scan of n >= 1 elements of `in` into `out` (distinct arrays); *total (nullable) gets the
+// sum.  tile holds at least 2 ceil(n / kScanTile) elements: the tile sums, then their scan.
+template <class T>
+void scan_exclusive(const T* in, T* out, int64_t n, T* total, T* tile, hipStream_t st) {
+    if (n <= kScanTile) {
+        hipLaunchKernelGGL(k_scan_exclusive<T>, dim3(1), dim3(kScanThreads), 0, st, in, out, n, total);
+        return;
+    }
+    const int nb = blocks_for(n, kScanTile);
+    hipLaunchKernelGGL(k_tile_sums<T>, dim3(nb), dim3(kScanThreads), 0, st, in, n, tile);
+    hipLaunchKernelGGL(k_scan_exclusive<T>, dim3(1), dim3(kScanThreads), 0, st, tile, tile + nb, (int64_t)nb, total);
+    hipLaunchKernelGGL(k_tile_scan<T>, dim3(nb), dim3(kScanThreads), 0, st, in, n, tile + nb, out);
+}
+
 }  // namespace
 
 // Scratch of one build; freed when the build returns.
@@ -726,6 +786,11 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     GET(hist, 256 * (int64_t)nb_sort); GET(offs, 256 * (int64_t)nb_sort); GET(total, 4);
     GET(left, nt); GET(right, nt); GET(first, nt); GET(last, nt);
     GET(entries, nt + 1); GET(kids, kWidth * (int64_t)(nt + 1)); GET(n_inner, nt + 1); GET(prefix, nt + 1);
+    // tile sums of the multi-workgroup scans (longest scan: the sort histograms or nt + 1 elements)
+    const int64_t scan_max = std::max<int64_t>(256 * (int64_t)nb_sort, (int64_t)nt + 1);
+    uint32_t* tsum32;
+    uint64_t* tsum64;
+    GET(tsum32, 2 * (scan_max / kScanTile + 2)); GET(tsum64, 2 * (scan_max / kScanTile + 2));
     int32_t *par_int, *par_leaf;
     uint32_t* flags;
     float4 *nlo, *nhi;
@@ -744,8 +809,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     uint32_t *ka = keys, *va = vals, *kb = keys2, *vb = vals2;
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, nt, shift, hist, nb_sort);
-        hipLaunchKernelGGL(k_scan_exclusive<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, hist, offs, 256 * (int64_t)nb_sort,
-                           (uint32_t*)nullptr);
+        scan_exclusive<uint32_t>(hist, offs, 256 * (int64_t)nb_sort, nullptr, tsum32, st);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb_sort), dim3(kSortThreads), 0, st, ka, va, kb, vb, nt, shift, offs,
                            nb_sort);
         uint32_t* t;
@@ -800,8 +864,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
                 ++depth;
                 hipLaunchKernelGGL(k_collapse_count, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries,
                                    base, n_level, kids, n_inner);
-                hipLaunchKernelGGL(k_scan_exclusive<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, n_inner, prefix,
-                                   (int64_t)n_level, total);
+                scan_exclusive<uint32_t>(n_inner, prefix, (int64_t)n_level, total, tsum32, st);
                 int32_t next_base = base + n_level;
                 hipLaunchKernelGGL(k_collapse_emit, dim3(blocks_for(n_level, 256)), dim3(256), 0, st, tv, entries,
                                    base, n_level, kids, prefix, next_base, tmp_nodes);
@@ -834,8 +897,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
             while (m > 1) {
                 hipLaunchKernelGGL(k_ploc_nn, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, clo, chi, nn);
                 hipLaunchKernelGGL(k_ploc_flags, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl);
-                hipLaunchKernelGGL(k_scan_exclusive<uint64_t>, dim3(1), dim3(kScanThreads), 0, st, fl, pre, (int64_t)m,
-                                   tot64);
+                scan_exclusive<uint64_t>(fl, pre, (int64_t)m, tot64, tsum64, st);
                 hipLaunchKernelGGL(k_ploc_merge, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl, pre,
                                    node_base, cid, clo, chi, cid2, clo2, chi2, left, right, cnt, nlo, nhi);
                 uint64_t t = 0;
