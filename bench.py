@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 latency"
 # VALU lane-operations per test as issued by the traversal kernel:
-OPS_PER_BOX = 18       # 6 fused slab distances, 10 min/max, 1 mul (exit growth), 1 compare
-OPS_PER_BOX_OCT = 11   # one-octant packet: 6 fused slab distances (exit growth folded in), 4 min/max, 1 compare
+# box tests are priced by the kernel's counting variant: 11 VALU ops in a one-octant packet (6 fused slab
+# distances with the exit growth folded in, 4 min/max, 1 compare), 14 with one mixed axis, 18 in general
+# (6 fused slab distances, 10 min/max, 1 multiply for the exit growth, 1 compare)
 NODE_BYTES, TRI_BYTES = 128, 48   # one 4-wide node; one leaf triangle record
 OPS_PER_TRI = 42       # Moller-Trumbore as compiled: 28 mul/FMA (2 cross, 4 dot, 3 scalings by 1/det, u+v), 3 subs,
                        # 1 reciprocal, 7 compares, 2 selects, 1 move
@@ -436,18 +437,18 @@ def main():
         st = ctx.read_stats(reset=True)
         box = st["box_lane"] / args.steps
         tri = st["tri_lane"] / args.steps
-        box_oct = st["box_lane_octant"] / args.steps
-        ops = box_oct * OPS_PER_BOX_OCT + (box - box_oct) * OPS_PER_BOX + tri * OPS_PER_TRI
+        box_ops_launch = st["box_ops"] / args.steps
+        ops = box_ops_launch + tri * OPS_PER_TRI
         achieved = ops / render_s / 1e12
         rays = st["rays"] / args.steps
-        box_ops = (box_oct * OPS_PER_BOX_OCT + (box - box_oct) * OPS_PER_BOX) / max(box, 1)
+        box_ops = box_ops_launch / max(box, 1)
         logical = st["node_wave"] / args.steps * NODE_BYTES + st["tri_wave"] / args.steps * TRI_BYTES
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
                            "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                            "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
                                           "wave_node_visits": st["node_wave"] / args.steps,
                                           "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
-                                          "one_octant_box_fraction": box_oct / max(box, 1),
+                                          "valu_ops_per_box_test": box_ops,
                                           "valu_ops": ops, "logical_scene_bytes": logical}}
         out["test_rates"] = {"ray_box_tests_per_s": box / render_s, "ray_tri_tests_per_s": tri / render_s,
                              "valu_ceiling_box_tests_per_s": ALU_PEAK_TOPS * 1e12 / box_ops,

@@ -347,8 +347,9 @@ vf_status vf_set_stats(vf_ctx* ctx, int32_t enable);
 /* Read (and optionally reset) the counters: out[0] rays, out[1] inner-node
  * visits per lane, out[2] ray-box tests, out[3] ray-triangle tests,
  * out[4] wave-level node visits, out[5] wave-level triangle loads,
- * out[6] the box tests of out[2] made in packets whose rays share one direction
- * octant (slab planes fixed), out[7] hits.  Synchronises the device. */
+ * out[6] VALU operations of the box tests (11 per test in a packet whose rays share
+ * one direction octant, 14 where they differ in the sign of one axis, 18 otherwise),
+ * out[7] hits.  Synchronises the device. */
 vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset);
 
 /* Render-kernel timing: while enabled (1), vf_step and vf_render record a pair of

@@ -53,13 +53,33 @@ __device__ __forceinline__ float safe_inv(float x) {
 }
 
 struct TraceStats {
-    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_oct;
+    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_ops;
 };
 
-// OCT >= 0: every ray of the packet has the direction octant OCT (bit set = negative component, by
-// the sign bit, as the reciprocal takes it), so the near and far planes of each slab are known at
-// compile time; OCT < 0: rays of several octants, both planes tested per axis.
-template <int NR, bool STATS, int OCT>
+// VALU operations of one ray-box test by the axes whose direction sign is fixed for the packet
+__host__ __device__ constexpr int box_test_ops(int fix) {
+    return fix == 7 ? 11 : fix == 0 ? 18 : 14;   // one axis mixed: 14
+}
+
+// One slab of the box test.  A fixed axis (every ray of the packet has the sign SGNA there, by the
+// sign bit, as the reciprocal takes it) knows its near and far plane at compile time and takes the
+// exit growth from the grown reciprocal; a mixed axis orders the two plane distances per lane.
+template <bool FIXA, bool SGNA>
+__device__ __forceinline__ void slab(float lo, float hi, float inv, float oi, float ing, float oig, float grow2,
+                                     float& tn, float& tf) {
+    if constexpr (FIXA) {
+        tn = fmaf(SGNA ? hi : lo, inv, oi);
+        tf = fmaf(SGNA ? lo : hi, ing, oig);
+    } else {
+        const float t0 = fmaf(lo, inv, oi), t1 = fmaf(hi, inv, oi);
+        tn = fminf(t0, t1);
+        tf = fmaxf(t0, t1) * grow2;
+    }
+}
+
+// FIX: bit a set = every ray of the packet has the direction sign of bit a of SGN on axis a (set =
+// negative).  FIX = 7: one octant, all slab planes known at compile time; FIX = 0: the general test.
+template <int NR, bool STATS, int FIX, int SGN>
 __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&valid)[NR], const float o[3],
                                              const float (&d)[NR][3], float t_near, float t_far,
                                              float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
@@ -99,8 +119,8 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             ing[r][k] = inv[r][k] * grow2;
             oig[r][k] = oi[r][k] * grow2;
         }
-    int oct = OCT;
-    if constexpr (OCT < 0) {
+    int oct = SGN;
+    if constexpr (FIX != 7) {
         oct = (d[0][0] < 0.f ? 1 : 0) | (d[0][1] < 0.f ? 2 : 0) | (d[0][2] < 0.f ? 4 : 0);
         oct = uniform_i(oct);
     }
@@ -120,7 +140,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             // them keeps the node one run of 16-dword loads
             if constexpr (kWidth == 4) {
                 asm volatile("" ::"s"(w[28]), "s"(w[31]));
-                if constexpr (OCT >= 0) asm volatile("" ::"s"(w[29]), "s"(w[30]));
+                if constexpr (FIX == 7) asm volatile("" ::"s"(w[29]), "s"(w[30]));
             } else {
 #pragma unroll
                 for (int i = kOrderWord; i < kNodeWords; ++i) asm volatile("" ::"s"(w[i]));
@@ -129,7 +149,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 ts.node_wave += 1;
                 ts.node_lane += n_valid;
                 ts.box_lane += kWidth * n_valid;
-                if (OCT >= 0) ts.box_oct += kWidth * n_valid;
+                ts.box_ops += (unsigned long long)box_test_ops(FIX) * kWidth * n_valid;
             }
             // bit k: some ray of the packet enters child k's box (empty slots hold a box no ray enters)
             uint32_t hb = 0;
@@ -139,15 +159,16 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 const float loy = __uint_as_float(w[2 * kWidth + k]), hiy = __uint_as_float(w[3 * kWidth + k]);
                 const float loz = __uint_as_float(w[4 * kWidth + k]), hiz = __uint_as_float(w[5 * kWidth + k]);
                 uint64_t m = 0;   // lanes with a ray entering the box (the union over the lane's rays)
-                if constexpr (OCT >= 0) {
-                    const float nx = (OCT & 1) ? hix : lox, fx = (OCT & 1) ? lox : hix;
-                    const float ny = (OCT & 2) ? hiy : loy, fy = (OCT & 2) ? loy : hiy;
-                    const float nz = (OCT & 4) ? hiz : loz, fz = (OCT & 4) ? loz : hiz;
+                if constexpr (FIX != 0) {
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        const float tnx = fmaf(nx, inv[r][0], oi[r][0]), tfx = fmaf(fx, ing[r][0], oig[r][0]);
-                        const float tny = fmaf(ny, inv[r][1], oi[r][1]), tfy = fmaf(fy, ing[r][1], oig[r][1]);
-                        const float tnz = fmaf(nz, inv[r][2], oi[r][2]), tfz = fmaf(fz, ing[r][2], oig[r][2]);
+                        float tnx, tfx, tny, tfy, tnz, tfz;
+                        slab<(FIX & 1) != 0, (SGN & 1) != 0>(lox, hix, inv[r][0], oi[r][0], ing[r][0], oig[r][0],
+                                                             grow2, tnx, tfx);
+                        slab<(FIX & 2) != 0, (SGN & 2) != 0>(loy, hiy, inv[r][1], oi[r][1], ing[r][1], oig[r][1],
+                                                             grow2, tny, tfy);
+                        slab<(FIX & 4) != 0, (SGN & 4) != 0>(loz, hiz, inv[r][2], oi[r][2], ing[r][2], oig[r][2],
+                                                             grow2, tnz, tfz);
                         const float t0 = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, t_near));
                         const float t1 = fminf(fminf(tfx, tfy), fminf(tfz, tb_box[r]));
                         m |= __ballot(t0 <= t1);
@@ -408,23 +429,40 @@ k_render(RenderArgs a) {
             m_neg[c] |= __ballot(valid[k] && signbit(d[k][c]));
             m_pos[c] |= __ballot(valid[k] && !signbit(d[k][c]));
         }
-    const bool one_oct = (m_neg[0] == 0 || m_pos[0] == 0) && (m_neg[1] == 0 || m_pos[1] == 0) &&
-                         (m_neg[2] == 0 || m_pos[2] == 0);
-    const int pk_oct = (m_neg[0] ? 1 : 0) | (m_neg[1] ? 2 : 0) | (m_neg[2] ? 4 : 0);
-#define VF_TRACE(O) trace_packet<NR, STATS, O>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts)
-    if (!VF_OCTANT_PACKETS || !one_oct) {
-        VF_TRACE(-1);
-    } else {
-        switch (pk_oct) {
-            case 0: VF_TRACE(0); break;
-            case 1: VF_TRACE(1); break;
-            case 2: VF_TRACE(2); break;
-            case 3: VF_TRACE(3); break;
-            case 4: VF_TRACE(4); break;
-            case 5: VF_TRACE(5); break;
-            case 6: VF_TRACE(6); break;
-            default: VF_TRACE(7); break;
-        }
+    // axes on which every ray of the packet has one sign, and those signs
+    int fix = 0, sgn = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (m_neg[c] == 0 || m_pos[c] == 0) fix |= 1 << c;
+        if (m_neg[c] != 0) sgn |= 1 << c;
+    }
+    sgn &= fix;
+    if (!VF_OCTANT_PACKETS) fix = 0;
+    if (!VF_PARTIAL_OCTANT && fix != 7) fix = 0;
+    if (__builtin_popcount(fix) < 2) fix = 0;       // two or three mixed axes: the general test
+#define VF_TRACE(F, S) trace_packet<NR, STATS, F, S>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts)
+    switch (fix == 0 ? 0 : (fix << 3) | sgn) {
+        case (7 << 3) | 0: VF_TRACE(7, 0); break;
+        case (7 << 3) | 1: VF_TRACE(7, 1); break;
+        case (7 << 3) | 2: VF_TRACE(7, 2); break;
+        case (7 << 3) | 3: VF_TRACE(7, 3); break;
+        case (7 << 3) | 4: VF_TRACE(7, 4); break;
+        case (7 << 3) | 5: VF_TRACE(7, 5); break;
+        case (7 << 3) | 6: VF_TRACE(7, 6); break;
+        case (7 << 3) | 7: VF_TRACE(7, 7); break;
+        case (6 << 3) | 0: VF_TRACE(6, 0); break;       // x mixed
+        case (6 << 3) | 2: VF_TRACE(6, 2); break;
+        case (6 << 3) | 4: VF_TRACE(6, 4); break;
+        case (6 << 3) | 6: VF_TRACE(6, 6); break;
+        case (5 << 3) | 0: VF_TRACE(5, 0); break;       // y mixed
+        case (5 << 3) | 1: VF_TRACE(5, 1); break;
+        case (5 << 3) | 4: VF_TRACE(5, 4); break;
+        case (5 << 3) | 5: VF_TRACE(5, 5); break;
+        case (3 << 3) | 0: VF_TRACE(3, 0); break;       // z mixed
+        case (3 << 3) | 1: VF_TRACE(3, 1); break;
+        case (3 << 3) | 2: VF_TRACE(3, 2); break;
+        case (3 << 3) | 3: VF_TRACE(3, 3); break;
+        default: VF_TRACE(0, 0); break;
     }
 #undef VF_TRACE
     if (vw.swarm != 0) trace_members<NR>(a, vw, slot, sc.n_tris, valid, o, d, t_best, id_best);
@@ -456,7 +494,7 @@ k_render(RenderArgs a) {
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
         unsigned long long v[7] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
-                                   ts.box_oct};
+                                   ts.box_ops};
         unsigned long long rays = 0;
         for (int k = 0; k < NR; ++k) rays += valid[k] ? 1 : 0;
         for (int off = 32; off > 0; off >>= 1) {

@@ -22,6 +22,9 @@ constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
 #ifndef VF_OCTANT_PACKETS
 #define VF_OCTANT_PACKETS 1   // packets of one ray octant take the traversal with fixed slab planes
 #endif
+#ifndef VF_PARTIAL_OCTANT
+#define VF_PARTIAL_OCTANT 1   // packets mixed in one axis fix the slab planes of the other two
+#endif
 #ifndef VF_RENDER_WAVES
 #define VF_RENDER_WAVES 1
 #endif

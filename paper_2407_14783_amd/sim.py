@@ -287,7 +287,7 @@ class Context:
     def read_stats(self, reset=True):
         out = (ctypes.c_uint64 * 8)()
         check(lib.vf_stats_read(self.h, out, 1 if reset else 0), "vf_stats_read")
-        keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_lane_octant", "hits")
+        keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_ops", "hits")
         return dict(zip(keys, list(out)))
 
     def mem_usage(self):
