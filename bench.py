@@ -231,10 +231,13 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
     """4,096 agents over the 8 room-graph scenes (Dirichlet split), half 64x64 and half 128x128 depth."""
     import torch
     from workloads import agents, scenes
+    from paper_2407_14783_amd.serving import ROOM_LEAF_SIZE
     scs = scenes.multi_scene_set(seed=6)
+    ctx.set_bvh_leaf_size(ROOM_LEAF_SIZE)      # room graphs: leaves of at most 3 triangles
     t0 = time.perf_counter()
     sids = [ctx.build_scene(s["verts"], s["tris"], s["rgb"]) for s in scs]
     build_s = time.perf_counter() - t0
+    ctx.set_bvh_leaf_size(4)
     counts = agents.multi_scene_split(6, 4096, 8)
     st = np.concatenate([agents.room_graph_starts(60 + j, int(c), scs[j], params) for j, c in enumerate(counts)])
     scene_of = np.repeat(np.arange(8), counts)
@@ -271,6 +274,7 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
            "scene_triangles": [int(i["n_tris"]) for i in infos],
            "scene_bytes": [int(i["bytes"]) for i in infos],
            "scene_build_device_ms": [round(float(i["build_ms"]), 2) for i in infos],
+           "bvh_leaf_size": int(infos[0]["leaf_max"]),
            "scene_build_wall_s_incl_upload": build_s}
     tk = committed_traffic("render_multiscene4096_pmc.md")
     if tk:

@@ -339,6 +339,14 @@ vf_status vf_set_launch_mode(vf_ctx* ctx, int32_t mode);
 enum { VF_BVH_CLUSTER = 0, VF_BVH_RADIX = 1 };
 vf_status vf_set_bvh_builder(vf_ctx* ctx, int32_t builder);
 
+/* Largest number of triangles in a BVH leaf for later scene builds, 1..4 (the
+ * default 4; vf_scene_info.leaf_max reports a scene's).  Subtrees of at most this
+ * many triangles become leaves, and free child slots are filled by splitting
+ * leaf-sized subtrees further.  Scenes of large flat faces (rooms) traverse
+ * faster with 3, scenes of long thin triangles (the forest's trunks) with 4.
+ * VF_EINVAL outside 1..4. */
+vf_status vf_set_bvh_leaf_size(vf_ctx* ctx, int32_t max_tris);
+
 /* Enable (1) / disable (0) traversal statistics: while enabled, vf_step and
  * vf_render use a counting variant of the render kernel that accumulates node
  * visits, box tests, triangle tests and rays into the context's counters. */

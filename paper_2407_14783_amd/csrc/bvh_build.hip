@@ -13,7 +13,7 @@
 //   6. collapse      level by level: each wide node takes the two children of its
 //                    binary node and opens the child of largest surface area among
 //                    those too big for a leaf until it has kWidth; free slots are then
-//                    filled by splitting leaf-sized subtrees; children with <= kLeafMax
+//                    filled by splitting leaf-sized subtrees; children with <= leaf_max
 //                    triangles become leaves (a contiguous sorted range)
 //   7. bounds        bottom-up per level (deepest first), leaf boxes padded by a
 //                    few ulps, plus per-octant near-to-far child orders
@@ -509,6 +509,7 @@ struct TreeView {
     const int32_t* last;
     const float4* nlo;   // inner-node boxes
     const float4* nhi;
+    int leaf_max;        // subtrees of at most this many triangles become leaves (1..kLeafMax)
     __device__ int count(int32_t r) const { return r >= 0 ? last[r] - first[r] + 1 : 1; }
     __device__ int start(int32_t r) const { return r >= 0 ? first[r] : -r - 1; }
     __device__ float area(int32_t r) const {
@@ -540,7 +541,7 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
             int best = -1;
             float besta = -1.0f;
             for (int k = 0; k < nk; ++k) {
-                if (c[k] >= 0 && tv.count(c[k]) > kLeafMax) {
+                if (c[k] >= 0 && tv.count(c[k]) > tv.leaf_max) {
                     float ar = tv.area(c[k]);
                     if (ar > besta) { besta = ar; best = k; }
                 }
@@ -570,7 +571,7 @@ __global__ void k_collapse_count(TreeView tv, const int32_t* __restrict__ entrie
     uint32_t ni = 0;
     for (int k = 0; k < kWidth; ++k) {
         kids[kWidth * (int64_t)e + k] = c[k];
-        if (c[k] != kEmpty && c[k] >= 0 && tv.count(c[k]) > kLeafMax) ++ni;
+        if (c[k] != kEmpty && c[k] >= 0 && tv.count(c[k]) > tv.leaf_max) ++ni;
     }
     n_inner[e] = ni;
 }
@@ -587,7 +588,7 @@ __global__ void k_collapse_emit(TreeView tv, int32_t* __restrict__ entries, int3
         int32_t entry;
         if (c == kEmpty) {
             entry = kEmptyChild;
-        } else if (c >= 0 && tv.count(c) > kLeafMax) {
+        } else if (c >= 0 && tv.count(c) > tv.leaf_max) {
             entry = next_base + (int32_t)at;
             entries[entry] = c;
             ++at;
@@ -844,7 +845,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
         n_nodes = 1;
         depth = 1;
     } else {
-        TreeView tv{left, right, first, last, nlo, nhi};
+        TreeView tv{left, right, first, last, nlo, nhi, ctx->bvh_leaf};
         // collapse the binary tree below `root` level by level; *too_deep when the wide tree would
         // exceed the traversal's depth bound
         auto collapse = [&](int32_t root, const uint32_t* leaf_vals, bool* too_deep) -> vf_status {
@@ -985,7 +986,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     out->info.n_leaves = 0;
     out->info.bytes = total_bytes;
     out->info.depth = depth;
-    out->info.leaf_max = kLeafMax;
+    out->info.leaf_max = ctx->bvh_leaf;
     for (int k = 0; k < 3; ++k) {
         out->info.bounds_lo[k] = bnd[6 + k];
         out->info.bounds_hi[k] = bnd[9 + k];

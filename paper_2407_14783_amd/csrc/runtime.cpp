@@ -653,6 +653,13 @@ vf_status vf_set_bvh_builder(vf_ctx* ctx, int32_t builder) {
     return VF_OK;
 }
 
+vf_status vf_set_bvh_leaf_size(vf_ctx* ctx, int32_t max_tris) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_bvh_leaf_size: NULL context");
+    if (max_tris < 1 || max_tris > kLeafMax) return fail(VF_EINVAL, "vf_set_bvh_leaf_size: size out of range");
+    ctx->bvh_leaf = max_tris;
+    return VF_OK;
+}
+
 vf_status vf_set_stats(vf_ctx* ctx, int32_t enable) {
     if (!ctx) return fail(VF_EINVAL, "vf_set_stats: NULL context");
     ctx->stats = enable != 0;

@@ -191,6 +191,7 @@ struct vf_ctx {
     bool stats = false;
     int32_t launch_mode = VF_LAUNCH_AUTO;
     int32_t bvh_builder = VF_BVH_CLUSTER;
+    int32_t bvh_leaf = vf::kLeafMax;    // leaf size of later builds (1..kLeafMax)
     std::vector<vf::Counters> counters;
     vf::SwarmTable swarm{};                // device copy of the swarm lists (n = 0: none)
     int64_t swarm_bytes = 0;

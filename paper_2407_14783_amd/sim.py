@@ -267,6 +267,10 @@ class Context:
         code = {"cluster": capi.VF_BVH_CLUSTER, "radix": capi.VF_BVH_RADIX}[builder]
         check(lib.vf_set_bvh_builder(self.h, code), "vf_set_bvh_builder")
 
+    def set_bvh_leaf_size(self, max_tris):
+        """Largest number of triangles per BVH leaf (1..4) for later scene builds."""
+        check(lib.vf_set_bvh_leaf_size(self.h, int(max_tris)), "vf_set_bvh_leaf_size")
+
     def set_spatial_order(self, on):
         """Sort split-launch batches by (scene, position) before rendering (default on)."""
         check(lib.vf_set_spatial_order(self.h, 1 if on else 0), "vf_set_spatial_order")

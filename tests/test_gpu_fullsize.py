@@ -77,8 +77,11 @@ def test_multi_scene_4096_sampled(vf):
     64x64, half 128x128, in one launch."""
     sim, ctx = vf
     p = default_params()
+    from paper_2407_14783_amd.serving import ROOM_LEAF_SIZE
     scs = scenes.multi_scene_set(seed=6)
+    ctx.set_bvh_leaf_size(ROOM_LEAF_SIZE)          # as the benchmark builds the room graphs
     sids = [ctx.build_scene(s["verts"], s["tris"], s["rgb"]) for s in scs]
+    ctx.set_bvh_leaf_size(4)
     counts = agents.multi_scene_split(6, 4096, 8)
     st = np.concatenate([agents.room_graph_starts(60 + j, int(c), scs[j], p) for j, c in enumerate(counts)])
     scene_of = np.repeat(np.arange(8), counts)

@@ -518,30 +518,44 @@ def test_bvh_invariants_and_deterministic_rebuild(vf):
     ctx.free_scene(sid2)
 
 
-def test_bvh_builders_agree(vf):
-    """The clustered and the radix-tree BVH of the same scene: both valid, and the same images bit for bit
-    (the closest hit does not depend on the tree; ties go to the lower id either way)."""
+def test_bvh_builders_and_leaf_sizes_agree(vf):
+    """The clustered and the radix-tree BVH of the same scene, and leaves of 1 to 4 triangles: all valid,
+    and the same images bit for bit (the closest hit does not depend on the tree; ties go to the lower id
+    either way)."""
     sim, ctx = vf
     p = default_params()
-    outs = {}
+    configs = (("radix", 4), ("cluster", 4), ("cluster", 3), ("cluster", 1), ("radix", 2))
     for name, sc in (("forest", scenes.forest(seed=3, n_trees=500)), ("room graph", scenes.room_graph(7, 20000))):
         if name == "forest":
             states = agents.forest_starts(4, 6, sc, p)
         else:
             states = agents.room_graph_starts(8, 6, sc, p)
-        for builder in ("radix", "cluster"):
+        outs = {}
+        for builder, leaf in configs:
             ctx.set_bvh_builder(builder)
+            ctx.set_bvh_leaf_size(leaf)
             sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
-            assert ctx.scene_info(sid)["builder"] == builder
-            header(f"BVH builders: {name}, {builder} tree")
-            _check_bvh(ctx, sid, sc)
-            outs[(name, builder)] = _render(ctx, sim, sid, states)
+            info = ctx.scene_info(sid)
+            assert info["builder"] == builder and info["leaf_max"] == leaf
+            header(f"BVH builds: {name}, {builder} tree, leaves of <= {leaf}")
+            nodes, _ = _check_bvh(ctx, sid, sc)
+            c = nodes["child"]
+            leaf_c = c[(c < 0) & (c != -2 ** 31)]
+            assert (((-leaf_c.astype(np.int64) - 1) & 7) + 1).max() <= leaf
+            outs[(builder, leaf)] = _render(ctx, sim, sid, states)
             ctx.free_scene(sid)
-        for a, b in zip(outs[(name, "radix")][:3], outs[(name, "cluster")][:3]):
-            assert np.array_equal(a, b), f"{name}: images differ between the two trees"
-        fr = _check_agents(sc, states[:2], *outs[(name, "cluster")], (64, 64), label=f"{name} cluster")
+        ref = outs[configs[0]]
+        for key in configs[1:]:
+            for a, b in zip(ref[:3], outs[key][:3]):
+                assert np.array_equal(a, b), f"{name}: images differ between {configs[0]} and {key}"
+        fr = _check_agents(sc, states[:2], *outs[("cluster", 4)], (64, 64), label=f"{name} cluster")
         assert np.mean(fr) < 0.02
     ctx.set_bvh_builder("cluster")
+    ctx.set_bvh_leaf_size(4)
+    with pytest.raises(Exception):
+        ctx.set_bvh_leaf_size(5)
+    with pytest.raises(Exception):
+        ctx.set_bvh_leaf_size(0)
 
 
 def _look_quat(f):
