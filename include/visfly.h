@@ -170,9 +170,11 @@ vf_status vf_create(int device, size_t hbm_budget_bytes, vf_ctx** out);
 vf_status vf_destroy(vf_ctx* ctx);
 
 /* Build a scene (Sec. III-B: triangle-mesh scenes) on the device: per-triangle
- * bounds and centroids, 30-bit Morton codes, a stable LSD radix sort, the
- * binary radix tree of Karras (HPG 2012), collapse to a 4-wide BVH, bottom-up
- * bounds and per-octant child orders.  verts [V][3] float32 [dev], tris [T][3]
+ * bounds and centroids, 30-bit Morton codes (one scale for the three axes), a
+ * stable LSD radix sort, a binary tree by locally-ordered clustering of the
+ * sorted triangles (or the Morton radix tree; see vf_set_bvh_builder), collapse
+ * to a 4-wide BVH with leaves of at most vf_set_bvh_leaf_size triangles,
+ * bottom-up bounds and per-octant child orders.  verts [V][3] float32 [dev], tris [T][3]
  * int32 [dev] (indices must be in [0, V); checked on the device, VF_EINVAL if
  * violated), tri_rgb [T][3] uint8 [dev] or NULL (grey).  The inputs are copied;
  * the caller may free them after the call returns.  Synchronous: returns when

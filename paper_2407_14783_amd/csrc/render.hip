@@ -8,10 +8,15 @@
 // (a lane-select write and v_readlane, the stack pointer in an SGPR).  Children are
 // pushed far-to-near using the node's precomputed order for the packet's
 // direction octant, so the nearest child is popped first and lanes that have
-// found a closer hit cull the rest by their per-lane t.
+// found a closer hit cull the rest by their per-lane t.  The traversal is
+// compiled for each combination of fixed ray-direction signs a packet can have
+// (one octant: 8; one mixed axis: 12; the general case): where every ray of the
+// packet has the same sign on an axis, the near and far slab planes of that axis
+// are known at compile time and the box test drops its per-axis min/max.
 //
-// Launch: one workgroup = 4 wavefronts = 4 tiles of one agent; the grid covers
-// n agents x ceil(tiles(max_h, max_w) / 4) groups.  Workgroups are remapped so
+// Launch: one workgroup = kWavesPerBlock wavefronts (one by default) = that many
+// tiles of one agent; the grid covers n agents x ceil(tiles(max_h, max_w) /
+// kWavesPerBlock) groups.  Workgroups are remapped so
 // each XCD (workgroup id mod 8) processes a contiguous range of agents, keeping
 // one agent's (and, with agents grouped by scene, one scene's) traffic in one L2.
 //
