@@ -78,6 +78,20 @@ def copy_calibration():
 TRAFFIC_SOURCES = ("render.hip", "vf_internal.h", "dynamics.h", "bvh_build.hip")
 
 
+def traffic_source_hash():
+    """Hash of the code (comments and whitespace removed) of the sources the counter records depend on."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2407_14783_amd", "csrc")
+    parts = []
+    for f in TRAFFIC_SOURCES:
+        text = open(os.path.join(csrc, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        parts.append(" ".join(text.split()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
+
+
 def committed_traffic(name="render_forest256_pmc.md"):
     """(fetch_kib, write_kib) per dispatch from a profiles/ counter summary if the render kernel's
     sources and the BVH build (which lays out what it reads) still hash as when the counters were taken,
@@ -90,9 +104,7 @@ def committed_traffic(name="render_forest256_pmc.md"):
     if not line:
         return None
     kv = dict(tok.split("=") for tok in line[0].split(":", 1)[1].split())
-    csrc = os.path.join(ROOT, "paper_2407_14783_amd", "csrc")
-    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                for f in TRAFFIC_SOURCES)).hexdigest()[:16]
+    h = traffic_source_hash()
     if h != kv.get("source_sha256_16"):
         return None
     return float(kv["fetch"]), float(kv["write"])
