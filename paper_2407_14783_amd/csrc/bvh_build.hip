@@ -376,9 +376,9 @@ __global__ void k_binary_bounds(const int32_t* __restrict__ left, const int32_t*
 // Clusters start as the leaves in Morton order.  Each pass, every cluster finds the
 // neighbour within kPlocRadius positions whose merged box has the smallest surface
 // area; mutual pairs merge into a new inner node placed at the lower position, and
-// the cluster array is compacted.  Pairs are ordered by (area, lower index, higher
-// index), so the globally best pair is always mutual and every pass merges at least
-// once.  Inner nodes are numbered by pass and prefix sum (deterministic); a node's
+// the cluster array is compacted.  Pairs are ordered by area, then by a symmetric
+// tie order (see tie_before), so the globally best pair is always mutual and every
+// pass merges at least once.  Inner nodes are numbered by pass and prefix sum (deterministic); a node's
 // children are always from earlier passes, which the top-down range pass relies on.
 // Child references: inner node k >= 0, leaf -(i + 1) for Morton position i; after
 // the range pass leaves are renumbered to depth-first order, so every subtree is a
@@ -407,10 +407,24 @@ __global__ void k_ploc_init(const uint32_t* __restrict__ sorted_vals, int32_t nt
     chi[i] = thi[t];
 }
 
-// nearest neighbour of each of the m >= 2 clusters; on equal areas the lower index wins, which
-// with a fixed i is the (lower index, higher index) order of the pair
+// Order of the pairs (i, j) and (i, k) of equal merged area.  Normally the lower other index first
+// (the pair order (area, lower index, higher index)).  That merges a run of identical boxes one pair
+// per pass, so after a pass that merged under 1/32 of the clusters the next pass orders ties by index
+// distance, then the fixed buddy i ^ 1, then the lower index: identical boxes pair off as buddies.
+// Either order is symmetric in the pair and total with the area first, so the least pair is chosen by
+// both its members and every pass merges.
+__device__ __forceinline__ bool tie_before(int i, int j, int k) {
+    const int dj = j > i ? j - i : i - j, dk = k > i ? k - i : i - k;
+    if (dj != dk) return dj < dk;
+    const bool bj = j == (i ^ 1), bk = k == (i ^ 1);
+    if (bj != bk) return bj;
+    return j < k;
+}
+
+// nearest neighbour of each of the m >= 2 clusters: least merged surface area; equal areas by the lower
+// index, or by tie_before when spread_ties is set
 __global__ void k_ploc_nn(int32_t m, const float4* __restrict__ clo, const float4* __restrict__ chi,
-                          int32_t* __restrict__ nn) {
+                          int32_t spread_ties, int32_t* __restrict__ nn) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const float4 l = clo[i], h = chi[i];
@@ -421,7 +435,7 @@ __global__ void k_ploc_nn(int32_t m, const float4* __restrict__ clo, const float
     for (int j = j0; j <= j1; ++j) {
         if (j == i) continue;
         const float a = merged_area(l, h, clo[j], chi[j]);
-        if (bj < 0 || a < ba) { ba = a; bj = j; }
+        if (bj < 0 || a < ba || (spread_ties && a == ba && tie_before(i, j, bj))) { ba = a; bj = j; }
     }
     nn[i] = bj;   // m >= 2: some j exists
 }
@@ -895,8 +909,10 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
                                chi);
             std::vector<int32_t> pass_base;
             int32_t m = nt, node_base = 0;
+            int32_t spread_ties = 0;
             while (m > 1) {
-                hipLaunchKernelGGL(k_ploc_nn, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, clo, chi, nn);
+                hipLaunchKernelGGL(k_ploc_nn, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, clo, chi,
+                                   spread_ties, nn);
                 hipLaunchKernelGGL(k_ploc_flags, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl);
                 scan_exclusive<uint64_t>(fl, pre, (int64_t)m, tot64, tsum64, st);
                 hipLaunchKernelGGL(k_ploc_merge, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, nn, fl, pre,
@@ -910,6 +926,7 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
                     return fail(VF_EHIP, "scene build: clustering pass made no progress");
                 pass_base.push_back(node_base);
                 node_base += merges;
+                spread_ties = (int64_t)merges * 32 < (int64_t)m ? 1 : 0;
                 m = kept;
                 std::swap(cid, cid2);
                 std::swap(clo, clo2);

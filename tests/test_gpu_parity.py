@@ -558,6 +558,38 @@ def test_bvh_builders_and_leaf_sizes_agree(vf):
         ctx.set_bvh_leaf_size(0)
 
 
+def test_duplicate_geometry_builds_balanced(vf):
+    """Thousands of identical triangles (duplicated geometry): the clustering pairs identical boxes off in a
+    logarithmic number of passes (no fallback, shallow tree, fast build), and the duplicates resolve to the
+    lowest caller id on every pixel that sees them."""
+    sim, ctx = vf
+    p = default_params()
+    floor = scenes.floor_quad(half=20.0, z=-1.0)
+    one = scenes.plane_quad((4.0, -1.0, -0.5), (0.0, 2.0, 0.0), (0.0, 0.0, 2.0))
+    n_dup = 20000
+    verts = np.concatenate([floor["verts"], one["verts"]]).astype(np.float32)
+    tris = np.concatenate([floor["tris"], np.tile(one["tris"][:1] + 4, (n_dup, 1))]).astype(np.int32)
+    rgb = np.concatenate([floor["rgb"], np.tile(one["rgb"][:1], (n_dup, 1))]).astype(np.uint8)
+    sc = {"verts": verts, "tris": tris, "rgb": rgb}
+    sid = ctx.build_scene(verts, tris, rgb)
+    info = ctx.scene_info(sid)
+    header(f"duplicate geometry: {n_dup} identical triangles, build {info['build_ms']:.2f} ms, depth {info['depth']}")
+    assert info["builder"] == "cluster" and info["depth"] <= 16
+    assert info["build_ms"] < 50.0
+    _check_bvh(ctx, sid, sc)
+    states = agents.make_states([[0.0, 0.0, 0.0]], p)
+    depth, ids, rgb_out, offs = _render(ctx, sim, sid, states, hw=(32, 32), hfov=1.2)
+    ref = oren.render_view(states[0].astype(np.float64), sc, 32, 32, 1.2)
+    # every duplicate pixel is an exact tie (masked by the oracle); the GPU must resolve all of them to the
+    # lowest id, 2, and see the duplicated triangle on about as many pixels
+    dup_ref = int((ref["id"].reshape(-1) >= 2).sum())
+    dup_gpu = ids >= 2
+    assert dup_ref > 50 and np.all(ids[dup_gpu] == 2)
+    assert abs(int(dup_gpu.sum()) - dup_ref) <= 0.1 * dup_ref
+    compare_render(depth, ids, None, ref, 100.0, "duplicates")      # everything off the mask
+    ctx.free_scene(sid)
+
+
 def _look_quat(f):
     """Attitude whose body x axis (the camera axis) points along f, with no roll."""
     f = np.asarray(f, dtype=np.float64) / np.linalg.norm(f)
