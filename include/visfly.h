@@ -175,8 +175,8 @@ vf_status vf_destroy(vf_ctx* ctx);
  * sorted triangles (or the Morton radix tree; see vf_set_bvh_builder), collapse
  * to a 4-wide BVH with leaves of at most vf_set_bvh_leaf_size triangles,
  * bottom-up bounds and per-octant child orders.  verts [V][3] float32 [dev], tris [T][3]
- * int32 [dev] (indices must be in [0, V); checked on the device, VF_EINVAL if
- * violated), tri_rgb [T][3] uint8 [dev] or NULL (grey).  The inputs are copied;
+ * int32 [dev] (indices must be in [0, V) and the vertices they use finite;
+ * checked on the device, VF_EINVAL if violated), tri_rgb [T][3] uint8 [dev] or NULL (grey).  The inputs are copied;
  * the caller may free them after the call returns.  Synchronous: returns when
  * the scene is ready.  1 <= T < 2^27. */
 vf_status vf_scene_build(vf_ctx* ctx, const float* verts, int64_t V, const int32_t* tris, int64_t T,

@@ -60,6 +60,10 @@ __global__ void k_tri_prep(const float* __restrict__ verts, int64_t nv, const in
             a[k] = verts[3 * (int64_t)ia + k];
             b[k] = verts[3 * (int64_t)ib + k];
             c[k] = verts[3 * (int64_t)ic + k];
+            if (!(isfinite(a[k]) && isfinite(b[k]) && isfinite(c[k]))) {
+                atomicOr(err, kErrVertex);
+                a[k] = b[k] = c[k] = 0.f;   // keep the rest of the build finite until it is rejected
+            }
             lo[k] = fminf(a[k], fminf(b[k], c[k]));
             hi[k] = fmaxf(a[k], fmaxf(b[k], c[k]));
             ce[k] = 0.5f * lo[k] + 0.5f * hi[k];   // box centre: robust for degenerate triangles
@@ -820,6 +824,18 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     hipLaunchKernelGGL(k_tri_prep, dim3(nb_prep), dim3(kPrepThreads), 0, st, verts, nv, tris, nt, tlo, thi, cen,
                        partial, ctx->d_err);
     hipLaunchKernelGGL(k_reduce_bounds, dim3(1), dim3(kScanThreads), 0, st, partial, nb_prep, tlo, thi, nt, bounds);
+    {
+        // reject bad input before the passes that would work on it
+        uint32_t bad = 0;
+        VF_HIP(hipMemcpyAsync(&bad, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        VF_HIP(hipStreamSynchronize(st));
+        if (bad & (kErrTriIndex | kErrVertex)) {
+            const uint32_t zero = 0;
+            VF_HIP(hipMemcpy(ctx->d_err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice));
+            return fail(VF_EINVAL, (bad & kErrTriIndex) ? "vf_scene_build: triangle vertex index out of range"
+                                                        : "vf_scene_build: vertex coordinates must be finite");
+        }
+    }
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, 256)), dim3(256), 0, st, cen, nt, bounds, keys, vals);
     uint32_t *ka = keys, *va = vals, *kb = keys2, *vb = vals2;
     for (int shift = 0; shift < 32; shift += 8) {

@@ -728,6 +728,7 @@ vf_status vf_sync_check(vf_ctx* ctx, void* stream) {
     if (err & kErrView) m += " bad view (size or hfov);";
     if (err & kErrStack) m += " traversal stack overflow;";
     if (err & kErrTriIndex) m += " triangle vertex index out of range;";
+    if (err & kErrVertex) m += " vertex coordinate not finite;";
     if (err & kErrTriId) m += " triangle id out of range;";
     return fail(VF_EDEVICE, m);
 }

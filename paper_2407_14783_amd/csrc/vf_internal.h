@@ -67,6 +67,7 @@ enum : uint32_t {
     kErrStack = 1u << 4,      // traversal stack overflow
     kErrTriIndex = 1u << 5,   // scene build: vertex index out of range
     kErrTriId = 1u << 6,      // render_backward: tri id out of range
+    kErrVertex = 1u << 7,     // scene build: a triangle's vertex coordinate is not finite
 };
 
 // ---------------------------------------------------------------------------

@@ -676,6 +676,15 @@ def test_errors_are_reported_not_faults(vf):
     with pytest.raises(capi.VfError) as e:
         ctx.build_scene(sc["verts"], np.array([[0, 1, 10_000]], dtype=np.int32))
     assert e.value.status == capi.VF_EINVAL
+    # a non-finite vertex used by a triangle is rejected before the build works on it; the error does
+    # not stick to later calls
+    for bad_value in (float("nan"), float("inf")):
+        vbad = sc["verts"].copy()
+        vbad[sc["tris"][5, 1], 2] = bad_value
+        with pytest.raises(capi.VfError) as e:
+            ctx.build_scene(vbad, sc["tris"], sc["rgb"])
+        assert e.value.status == capi.VF_EINVAL and "finite" in str(e.value)
+    ctx.sync_check()
     with pytest.raises(capi.VfError) as e:
         ctx.free_scene(999)
     assert e.value.status == capi.VF_ENOSCENE
