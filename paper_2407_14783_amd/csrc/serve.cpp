@@ -311,10 +311,16 @@ static void worker_loop(vf_server* s) {
         if (progressed) s->cv_done.notify_all();
         bool any_busy = false;
         for (auto& a : s->arenas) any_busy |= a.busy;
-        if (any_busy)
-            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
-        else if (!progressed)
+        if (any_busy) {
+            // batches in flight: check their events again at once (a timed wait of a few microseconds
+            // sleeps for the kernel's timer slack, tens of microseconds, on every batch's latency);
+            // the lock is released meanwhile so submitters and waiters get in
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else if (!progressed) {
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        }
     }
 }
 
