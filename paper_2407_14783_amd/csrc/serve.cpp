@@ -18,7 +18,9 @@
 // bitwise the same alone or in any mix.
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cstdint>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -125,13 +127,46 @@ static void launch_batch(vf_server* s, SlotArena& a) {
         return;
     }
     char* h = (char*)a.host;
+    char* d = (char*)a.dev;
     vf_view* hv = (vf_view*)(h + a.off_views);
     int32_t* hi = (int32_t*)(h + a.off_idx);
     float* ha = (float*)(h + a.off_act);
+    // A depth-only batch renders a request that asked for a device depth buffer (and no host results)
+    // straight into that buffer, with no copy afterwards: every view's output offset then counts, in
+    // floats, from the lowest target address of the batch (the arena's depth section for the others),
+    // and the render's bound check spans up to the highest target's end.
+    std::vector<uintptr_t> target(a.reqs.size(), 0);
+    bool direct = !s->cfg.want_tri_id && !s->cfg.want_rgb;
+    uintptr_t base = 0;
+    int64_t span = 0;
+    if (direct) {
+        uintptr_t lo = UINTPTR_MAX, hi_end = 0;
+        int64_t p0 = 0;
+        for (size_t k = 0; k < a.reqs.size(); ++k) {
+            const Request* r = a.reqs[k];
+            const int64_t rpx = (int64_t)r->desc.H * r->desc.W * r->desc.n_env;
+            const uintptr_t t = (r->out.depth && !r->host) ? (uintptr_t)r->out.depth
+                                                           : (uintptr_t)(d + a.off_depth + 4 * p0);
+            if (t % 4 != 0) {
+                direct = false;
+                break;
+            }
+            target[k] = t;
+            lo = std::min(lo, t);
+            hi_end = std::max(hi_end, t + 4 * (uintptr_t)rpx);
+            p0 += rpx;
+        }
+        if (direct) {
+            base = lo;
+            span = (int64_t)((hi_end - lo) / 4);
+        }
+    }
     int64_t agent = 0, pix = 0;
     a.px_off.clear();
-    for (Request* r : a.reqs) {
+    for (size_t k = 0; k < a.reqs.size(); ++k) {
+        Request* r = a.reqs[k];
         a.px_off.push_back(pix);
+        const int64_t req_off = direct ? (int64_t)((target[k] - base) / 4) : pix;
         for (int32_t e = 0; e < r->desc.n_env; ++e) {
             vf_view& v = hv[agent];
             memset(&v, 0, sizeof(v));
@@ -143,14 +178,13 @@ static void launch_batch(vf_server* s, SlotArena& a) {
             v.near_clip = r->desc.near_clip;
             v.far_clip = r->desc.far_clip;
             v.miss_depth = r->desc.miss_depth;
-            v.out_offset = pix;
+            v.out_offset = req_off + (int64_t)e * r->desc.H * r->desc.W;
             hi[agent] = r->slots[e];
             memcpy(ha + 4 * agent, r->actions.data() + 4 * e, 16);
             pix += (int64_t)r->desc.H * r->desc.W;
             ++agent;
         }
     }
-    char* d = (char*)a.dev;
     hipError_t e = hipMemcpyAsync(d, h, a.off_depth, hipMemcpyHostToDevice, a.stream);
     StepArgs sa{(int32_t)n, (const int32_t*)(d + a.off_idx), s->state, s->n_slots, (const float*)(d + a.off_act),
                 s->ctx->d_err, s->dyn};
@@ -166,10 +200,10 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     ra.views = (const vf_view*)(d + a.off_views);
     ra.max_h = s->cfg.max_h;
     ra.max_w = s->cfg.max_w;
-    ra.depth = (float*)(d + a.off_depth);
+    ra.depth = direct ? (float*)base : (float*)(d + a.off_depth);
     ra.tri_id = s->cfg.want_tri_id ? (int32_t*)(d + a.off_ids) : nullptr;
     ra.rgb = s->cfg.want_rgb ? (uint8_t*)(d + a.off_rgb) : nullptr;
-    ra.out_pixels = px;
+    ra.out_pixels = direct ? span : px;
     ra.err = s->ctx->d_err;
     ra.stats = s->ctx->d_stats;
     ra.swarm = s->ctx->swarm;
@@ -194,7 +228,8 @@ static void launch_batch(vf_server* s, SlotArena& a) {
         Request* r = a.reqs[k];
         any_host |= r->host;
         int64_t rpx = (int64_t)r->desc.H * r->desc.W * r->desc.n_env, p0 = a.px_off[k];
-        if (r->out.depth && e == hipSuccess)
+        const bool written = direct && r->out.depth && !r->host;   // rendered in place
+        if (r->out.depth && !written && e == hipSuccess)
             e = hipMemcpyAsync(r->out.depth, d + a.off_depth + 4 * p0, rpx * 4, hipMemcpyDeviceToDevice, a.stream);
         if (r->out.tri_id && s->cfg.want_tri_id && e == hipSuccess)
             e = hipMemcpyAsync(r->out.tri_id, d + a.off_ids + 4 * p0, rpx * 4, hipMemcpyDeviceToDevice, a.stream);

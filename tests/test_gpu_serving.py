@@ -99,6 +99,56 @@ def test_result_alone_equals_mix_and_plain_step(setup):
     assert np.array_equal(st2.cpu().numpy()[target[2]], alone["state"])
 
 
+def test_depth_only_server_writes_device_buffers_in_place(setup):
+    """A depth-only server renders requests with device depth buffers straight into them: each buffer holds
+    the plain batched step's depth for its slots, guard elements past its end are untouched, and requests
+    taking host results in the same batches are unaffected."""
+    env = setup
+    from paper_2407_14783_amd import sim
+    rng = np.random.default_rng(17)
+    st = torch.as_tensor(env["table"]).cuda()
+    srv = _server(env, st, want_tri_id=False, want_rgb=False)
+    perm = {sc: list(rng.permutation(PER)) for sc in range(3)}
+    reqs = []
+    for k in range(30):
+        sc = int(rng.integers(0, 3))
+        n_env = int(rng.integers(1, 40))
+        take, perm[sc] = perm[sc][:n_env], perm[sc][n_env:]
+        hw = [(64, 64), (96, 96), (40, 56)][k % 3]
+        slots = (sc * PER + np.asarray(take)).astype(np.int32)
+        acts = agents.random_actions(100 + k, 1, len(take), env["p"])[0]
+        reqs.append((sc, hw, slots, acts))
+    header("serving: depth-only server, 30 requests, half into device buffers")
+    guard = 64
+    bufs, tickets = [], []
+    for k, (sc, hw, slots, acts) in enumerate(reqs):
+        n_px = slots.shape[0] * hw[0] * hw[1]
+        if k % 2 == 0:
+            buf = torch.full((n_px + guard,), -7.0).cuda()
+            bufs.append(buf)
+            tickets.append(srv.submit(env["sids"][sc], hw, slots, acts, out={"depth": buf}, host_results=False))
+        else:
+            bufs.append(None)
+            tickets.append(srv.submit(env["sids"][sc], hw, slots, acts))
+    results = [srv.wait(t, fetch=bufs[k] is None) for k, t in enumerate(tickets)]
+    srv.close()
+    for k, (sc, hw, slots, acts) in enumerate(reqs):
+        ref_state = torch.as_tensor(env["table"]).cuda()
+        n = slots.shape[0]
+        views, npx, offs, mh, mw = sim.make_views(n, env["sids"][sc], hw)
+        depth = torch.empty(npx).cuda()
+        env["ctx"].step(env["p"], ref_state, torch.as_tensor(acts).cuda(), views=views,
+                        env_idx=torch.as_tensor(slots).cuda(), max_hw=(mh, mw), depth=depth, out_pixels=npx)
+        env["ctx"].sync_check()
+        ref = depth.cpu().numpy()
+        if bufs[k] is not None:
+            got = bufs[k].cpu().numpy()
+            assert np.array_equal(got[:npx], ref), f"request {k}: device depth differs"
+            assert np.all(got[npx:] == -7.0), f"request {k}: write past the buffer"
+        else:
+            assert np.array_equal(results[k]["depth"], ref), f"request {k}: host depth differs"
+
+
 def test_same_slot_requests_apply_in_order(setup):
     env = setup
     rng = np.random.default_rng(9)
