@@ -95,15 +95,15 @@ static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 // Bytes a request needs in an arena (work list + outputs + state echo).
 static int64_t request_bytes(const vf_server_config& cfg, const vf_request_desc& d) {
     int64_t px = (int64_t)d.H * d.W * d.n_env;
-    int64_t b = (int64_t)d.n_env * ((int64_t)sizeof(vf_view) + 4 + 16 + 17 * 4 + 4);
+    int64_t b = (int64_t)d.n_env * ((int64_t)sizeof(vf_view) + 4 + 16 + 17 * 4);   // view, slot, action, state
     b += px * 4;                                  // depth
     if (cfg.want_tri_id) b += px * 4;
     if (cfg.want_rgb) b += px * 3;
-    return b + 8 * 256;                           // worst-case alignment of the eight arena sections
+    return b + 7 * 256;                           // worst-case alignment of the seven arena sections
 }
 
 static void launch_batch(vf_server* s, SlotArena& a) {
-    // lay out the arena: views | env idx | actions | depth | ids | rgb | state echo | render order
+    // lay out the arena: views | env idx | actions | depth | ids | rgb | state echo
     int64_t n = a.n_agents, px = a.n_px;
     a.off_views = 0;
     a.off_idx = align_up(a.off_views + n * (int64_t)sizeof(vf_view), 256);
@@ -112,8 +112,7 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     a.off_ids = align_up(a.off_depth + px * 4, 256);
     a.off_rgb = align_up(a.off_ids + (s->cfg.want_tri_id ? px * 4 : 0), 256);
     a.off_state = align_up(a.off_rgb + (s->cfg.want_rgb ? px * 3 : 0), 256);
-    const int64_t off_order = align_up(a.off_state + n * 17 * 4, 256);
-    int64_t end = align_up(off_order + n * 4, 256);
+    int64_t end = align_up(a.off_state + n * 17 * 4, 256);
     if (end > a.bytes) {   // admission sizes requests so this cannot happen; never launch past the arena
         s->worker_error = "batch larger than its arena";
         for (Request* r : a.reqs) {
@@ -207,11 +206,8 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     ra.err = s->ctx->d_err;
     ra.stats = s->ctx->d_stats;
     ra.swarm = s->ctx->swarm;
-    if (e == hipSuccess && s->ctx->spatial_order && n >= 64 && n <= kOrderMax) {
-        OrderArgs o{(int32_t)n, ra.env_idx, ra.state, ra.n_slots, ra.views, (int32_t*)(d + off_order)};
-        e = launch_order(o, a.stream);
-        ra.order = o.order;
-    }
+    // no spatial order here: for the server's batches (mostly one or two requests) the ordering kernel
+    // cost more than the cache locality it bought
     if (e == hipSuccess) e = launch_render(ra, false, false, a.stream);
     // gather the new states of the batch's env slots with the render's view of them, when a request of
     // the batch takes states back (host results or a device state buffer)
