@@ -313,10 +313,11 @@ vf_status vf_imu(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int3
 vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, const int32_t* slots,
                         const float half_extent[3], const uint8_t rgb[3]);
 
-/* Render order of split launches (vf_step split form, vf_render, the server): with enable != 0 (the
- * default) a batch of 64 .. 1024 agents is first sorted by (scene id, 2-D Morton code of position) in
- * one small kernel, so that the agents one XCD renders share a scene region and its L2 holds the part
- * of the BVH they touch.  The order changes which workgroup renders an agent, never the results. */
+/* Render order of split launches (vf_step split form, vf_render): with enable != 0 (the default) a
+ * batch of 64 .. 512 agents is first sorted by (scene id, 2-D Morton code of position) in one small
+ * kernel, so that the agents one XCD renders share a scene region and its L2 holds the part of the BVH
+ * they touch (larger batches, and the server's batches, are not ordered: there the ordering kernel
+ * costs more than it saves).  The order changes which workgroup renders an agent, never the results. */
 vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
 
 /* How vf_step with views launches its work.  VF_LAUNCH_SPLIT: a dynamics

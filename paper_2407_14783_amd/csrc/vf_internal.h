@@ -230,7 +230,8 @@ struct RenderArgs {
     SwarmTable swarm;
     DynConst dyn;
 };
-constexpr int kOrderMax = 1024;      // batches of 64 .. kOrderMax agents are put in spatial order
+constexpr int kOrderMax = 1024;      // capacity of the spatial-order kernel (agents per batch)
+constexpr int kOrderAutoMax = 512;   // split launches of 64 .. this many agents are put in spatial order
 struct OrderArgs {
     int32_t n;
     const int32_t* env_idx;

@@ -179,3 +179,32 @@ def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
         checked += 1
     assert checked >= 2
     ctx.free_scene(sid)
+
+
+def test_bptt_kept_ids_equal_rerendered(vf):
+    """Keeping every frame's hit ids in the forward (no renders in backward) and re-rendering each segment in
+    backward give the same gradients bit for bit: the same kernels see the same states and ids."""
+    sim, ctx = vf
+    from paper_2407_14783_amd import autograd as vag
+    p = default_params()
+    sc = scenes.forest(seed=3, n_trees=400)
+    n, H = 6, 20
+    s0 = agents.forest_starts(8, n, sc, p)
+    rng = np.random.default_rng(31)
+    acts = np.concatenate([rng.uniform(0.9, 1.15, (H, n, 1)) * p["g"], rng.uniform(-0.6, 0.6, (H, n, 3))],
+                          axis=2).astype(np.float32)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+    header("BPTT: kept hit ids vs re-rendered segments, 6 agents x 20 steps, k = 8")
+    grads = []
+    for keep in (True, False):
+        s0_t = _dev(s0).requires_grad_(True)
+        a_t = _dev(acts).requires_grad_(True)
+        states, depths = vag.rollout(ctx, p, s0_t, a_t, views, (mh, mw), npx, checkpoint_every=8, keep_ids=keep)
+        loss = torch.exp(-depths).view(H, n, -1).mean(2).sum() + 0.01 * (states[:, :, 0:3] ** 2).sum()
+        loss.backward()
+        grads.append((s0_t.grad.cpu().numpy(), a_t.grad.cpu().numpy(), loss.item()))
+    assert grads[0][2] == grads[1][2]
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    assert np.abs(grads[0][1]).max() > 0
+    ctx.free_scene(sid)

@@ -404,8 +404,8 @@ def test_multi_scene_mixed_resolution(vf):
 
 def test_spatial_order_changes_nothing(vf):
     """The (scene, position) render order of large batches moves work between workgroups only:
-    split steps and renders with and without it are bitwise equal, over two scenes, env slots,
-    mixed sizes and a batch just past the ordering threshold; every output pixel is written."""
+    split steps and renders with and without it are bitwise equal, over two scenes, env slots and
+    mixed sizes; every output pixel is written."""
     sim, ctx = vf
     p = default_params()
     scs = [scenes.forest(seed=3, n_trees=300), scenes.box_room(seed=1)]
