@@ -233,7 +233,7 @@ def run_load(server, scene_ids, reqs, rate=None, seed=0, device_out=None):
 ROOM_LEAF_SIZE = 3
 
 
-def bench_summary(sim_ctx, params, n_requests=4000, seed=7):
+def bench_summary(sim_ctx, params, n_requests=4000, seed=7, n_streams=3):
     """Serving measurement over the eight multi-scene room graphs (see the module docstring)."""
     from workloads import agents, scenes
     from . import sim
@@ -264,7 +264,7 @@ def bench_summary(sim_ctx, params, n_requests=4000, seed=7):
         sim_ctx.step(p, state, acts, views=views, env_idx=idx_t, max_hw=(mh, mw), depth=depth, out_pixels=npx)
     torch.cuda.synchronize()
     plain_fps = n_plain * reps / (time.perf_counter() - t0)
-    server = Server(sim_ctx, params, state, n_streams=3, max_batch_agents=8192, max_hw=(96, 96),
+    server = Server(sim_ctx, params, state, n_streams=n_streams, max_batch_agents=8192, max_hw=(96, 96),
                     budget_bytes=3 * (1 << 30))
     reqs = make_requests(seed, n_requests, 8, per, params)
     mean_env = float(np.mean([r[2].shape[0] for r in reqs]))
