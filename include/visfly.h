@@ -106,8 +106,8 @@ typedef struct vf_view {
     int32_t H, W;        /* image size, 1..1024 each */
     int32_t flags;       /* the agent's sensor-noise key (vf_sensor_noise); ignored by the renderer */
     float hfov;          /* horizontal field of view (rad), (0, pi) */
-    float near_clip;     /* hits closer than this are ignored (m) */
-    float far_clip;      /* hits farther than this are ignored (m) */
+    float near_clip;     /* hits closer than this are ignored (m); must be > 0 */
+    float far_clip;      /* hits farther than this are ignored (m); must be > near_clip */
     float miss_depth;    /* depth written where nothing is hit */
     int64_t out_offset;  /* first output pixel of this view */
     float mount_q[4];    /* camera orientation in the body frame (w, x, y, z) */

@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     vf_view vw = a.views[agent];
     bool ok = vw.scene_id >= 0 && vw.scene_id < a.n_scenes && vw.H >= 1 && vw.W >= 1 && vw.H <= a.max_h &&
               vw.W <= a.max_w && vw.out_offset >= 0 && vw.out_offset + (int64_t)vw.H * vw.W <= a.out_pixels &&
-              vw.hfov > 0.f && vw.hfov < 3.1415926f;
+              vw.hfov > 0.f && vw.hfov < 3.1415926f && vw.near_clip > 0.f && vw.far_clip > vw.near_clip;
     if (ok) ok = a.scenes[vw.scene_id].valid != 0;
     if (!ok) {
         if (threadIdx.x == 0) atomicOr(a.err, kErrView);

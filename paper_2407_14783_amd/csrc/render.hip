@@ -274,7 +274,12 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     // det == 0 needs no test of its own: 1/det is infinite, so u and v are infinite or
                     // NaN and one of the comparisons fails
                     const bool h = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t >= t_near);
-                    const bool take = h & ((t < t_best[r]) | ((t == t_best[r]) & ((uint32_t)id < (uint32_t)id_best[r])));
+                    // nearer, or as near with a lower id, as one unsigned compare of (depth bits, id): a
+                    // depth >= t_near > 0 (the view check rejects other clip ranges) orders by its bits; lanes
+                    // outside the image (best depth -1) are kept out by their flag
+                    const uint64_t key = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)id;
+                    const uint64_t bk = ((uint64_t)__float_as_uint(t_best[r]) << 32) | (uint32_t)id_best[r];
+                    const bool take = h & valid[r] & (key < bk);
                     t_best[r] = take ? t : t_best[r];
                     id_best[r] = take ? id : id_best[r];
                 }
@@ -343,7 +348,8 @@ __device__ __forceinline__ void trace_members(const RenderArgs& a, const vf_view
 __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) {
     uint32_t bits = 0;
     if (vw.scene_id < 0 || vw.scene_id >= a.n_scenes) bits |= kErrScene;
-    if (vw.H < 1 || vw.W < 1 || vw.H > a.max_h || vw.W > a.max_w || !(vw.hfov > 0.f && vw.hfov < 3.1415926f))
+    if (vw.H < 1 || vw.W < 1 || vw.H > a.max_h || vw.W > a.max_w || !(vw.hfov > 0.f && vw.hfov < 3.1415926f) ||
+        !(vw.near_clip > 0.f && vw.far_clip > vw.near_clip))
         bits |= kErrView;
     if (vw.out_offset < 0 || vw.out_offset + (int64_t)vw.H * vw.W > a.out_pixels) bits |= kErrPixels;
     if (bits == 0 && !a.scenes[vw.scene_id].valid) bits |= kErrScene;

@@ -726,7 +726,7 @@ vf_status vf_sync_check(vf_ctx* ctx, void* stream) {
     if (err & kErrScene) m += " bad scene id;";
     if (err & kErrSlot) m += " env slot out of range;";
     if (err & kErrPixels) m += " output pixels out of range;";
-    if (err & kErrView) m += " bad view (size or hfov);";
+    if (err & kErrView) m += " bad view (size, hfov or clip range);";
     if (err & kErrStack) m += " traversal stack overflow;";
     if (err & kErrTriIndex) m += " triangle vertex index out of range;";
     if (err & kErrVertex) m += " vertex coordinate not finite;";

@@ -63,7 +63,7 @@ enum : uint32_t {
     kErrScene = 1u << 0,      // scene id out of range or freed
     kErrSlot = 1u << 1,       // env_idx out of [0, n_slots)
     kErrPixels = 1u << 2,     // out_offset + H*W beyond out_pixels (or negative)
-    kErrView = 1u << 3,       // H, W outside [1, max], bad hfov
+    kErrView = 1u << 3,       // H, W outside [1, max], bad hfov, near <= 0 or far <= near
     kErrStack = 1u << 4,      // traversal stack overflow
     kErrTriIndex = 1u << 5,   // scene build: vertex index out of range
     kErrTriId = 1u << 6,      // render_backward: tri id out of range

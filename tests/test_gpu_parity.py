@@ -657,6 +657,15 @@ def test_errors_are_reported_not_faults(vf):
         ctx.sync_check()
     assert e.value.status == capi.VF_EDEVICE and "scene" in str(e.value)
     assert torch.all(depth == 3.0)
+    # clip ranges the renderer cannot order hits in (near <= 0, far <= near) -> bad view, nothing written
+    for near, far in ((0.0, 100.0), (-1.0, 100.0), (2.0, 2.0)):
+        views, npx, offs, mh, mw = sim.make_views(1, sid, (16, 16), near=near, far=far)
+        depth = torch.full((npx,), 3.0).cuda()
+        ctx.render(st, views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+        with pytest.raises(capi.VfError) as e:
+            ctx.sync_check()
+        assert e.value.status == capi.VF_EDEVICE and "clip" in str(e.value)
+        assert torch.all(depth == 3.0)
     # output capacity too small -> rejected on the device, nothing written
     views, npx, offs, mh, mw = sim.make_views(1, sid, (16, 16))
     ctx.render(st, views, max_hw=(mh, mw), depth=depth, out_pixels=npx - 1)
