@@ -34,8 +34,8 @@ METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 l
 # distances with the exit growth folded in, 4 min/max, 1 compare), 14 with one mixed axis, 18 in general
 # (6 fused slab distances, 10 min/max, 1 multiply for the exit growth, 1 compare)
 NODE_BYTES, TRI_BYTES = 128, 48   # one 4-wide node; one leaf triangle record
-OPS_PER_TRI = 42       # Moller-Trumbore as compiled: 28 mul/FMA (2 cross, 4 dot, 3 scalings by 1/det, u+v), 3 subs,
-                       # 1 reciprocal, 7 compares, 2 selects, 1 move
+OPS_PER_TRI = 40       # Moller-Trumbore as compiled: 28 mul/FMA (2 cross, 4 dot, 3 scalings by 1/det, u+v), 3 subs,
+                       # 1 reciprocal, 5 compares (the last a 64-bit (depth, id) compare), 2 selects, 1 move
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
 HBM_PEAK_GBPS = 8000.0
 
