@@ -386,8 +386,10 @@ vf_status vf_sync_check(vf_ctx* ctx, void* stream);
  * request that does not fit the arena blocks those behind it (no starvation);
  * a request touching an env slot that an in-flight or earlier queued request
  * touches waits for it, so each env sees its requests in submission order.
- * Results (depth, optional ids / colours, new states) come back to host memory;
- * latency is measured from submit to the completion of the batch.  Agents are
+ * Results (depth, optional ids / colours, new states) go to device buffers the
+ * request names and/or back to host memory; latency is measured from submit to the
+ * completion of the batch.  While batches are in flight the server's worker thread
+ * polls their completion without sleeping (one host core).  Agents are
  * independent, so a request's result does not depend on the batch it joins.
  * ------------------------------------------------------------------------- */
 typedef struct vf_server vf_server; /* opaque */
@@ -407,11 +409,14 @@ typedef struct vf_request_desc {
     float hfov, near_clip, far_clip, miss_depth;
 } vf_request_desc;
 
-/* Where a request's results go.  Device buffers (any may be NULL) receive them by
- * device-to-device copies on the batch's stream before the request completes:
- * depth [n_env][H][W] float32, tri_id [n_env][H][W] int32 (needs want_tri_id),
- * rgb [n_env][3][H][W] uint8 (needs want_rgb), state [n_env][17] float32.
- * host_results = 1 also keeps host copies for vf_server_wait. */
+/* Where a request's results go.  Device buffers (any may be NULL) receive them on
+ * the batch's stream before the request completes: depth [n_env][H][W] float32,
+ * tri_id [n_env][H][W] int32 (needs want_tri_id), rgb [n_env][3][H][W] uint8 (needs
+ * want_rgb), state [n_env][17] float32.  A server without ids and colours renders a
+ * request's depth straight into its depth buffer when the request keeps no host
+ * results (the buffer must be 4-byte aligned; otherwise, and for the other outputs,
+ * a device-to-device copy).  host_results = 1 also keeps host copies for
+ * vf_server_wait. */
 typedef struct vf_request_out {
     float* depth;
     int32_t* tri_id;
