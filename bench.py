@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--multi-scene-only", action="store_true",
                     help="run only the multi-scene batch and print its record (for counter runs)")
+    ap.add_argument("--no-cost-order", action="store_true",
+                    help="plain workgroup order (no longest-first order from the previous launch's work)")
     ap.add_argument("--no-spatial-order", action="store_true",
                     help="render agents in the given order instead of (scene, position) order")
     return ap.parse_args()
@@ -377,6 +379,7 @@ def main():
     acts_np = agents.random_actions(5, 200, n, params)
     ctx = sim.Context(0)
     ctx.set_spatial_order(not args.no_spatial_order)
+    ctx.set_cost_order(not args.no_cost_order)
     # the latency-bound single-agent case first, on an idle device
     box_room = None if args.no_extra else box_room_latency(ctx, sim, params)
     sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])

@@ -317,8 +317,17 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
  * batch of 64 .. 512 agents is first sorted by (scene id, 2-D Morton code of position) in one small
  * kernel, so that the agents one XCD renders share a scene region and its L2 holds the part of the BVH
  * they touch (larger batches, and the server's batches, are not ordered: there the ordering kernel
- * costs more than it saves).  The order changes which workgroup renders an agent, never the results. */
+ * costs more than it saves; nor are launches put in cost order, see vf_set_cost_order).  The order
+ * changes which workgroup renders an agent, never the results. */
 vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
+
+/* Workgroup order of split launches of 1,024 .. 32,768 packets (vf_step split form, vf_render): with
+ * enable != 0 (the default) each render records the traversal work of every packet in per-stream scratch,
+ * and the next launch on that stream with the same number of views and packets per view first runs one
+ * small kernel that puts each XCD's workgroups in decreasing order of that work, so the longest packets
+ * start first instead of running alone at the end of the launch.  The first launch of a shape keeps the
+ * plain order.  The order changes which workgroup renders a packet, never the results. */
+vf_status vf_set_cost_order(vf_ctx* ctx, int32_t enable);
 
 /* How vf_step with views launches its work.  VF_LAUNCH_SPLIT: a dynamics
  * kernel (one thread per agent) then the render kernel, two launches on the

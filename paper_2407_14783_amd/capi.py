@@ -26,7 +26,7 @@ EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_sc
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
             "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_set_bvh_builder", "vf_set_bvh_leaf_size", "vf_server_create",
             "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
-            "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_timing", "vf_timing_read")
+            "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_cost_order", "vf_set_timing", "vf_timing_read")
 
 
 class DynParams(ctypes.Structure):
@@ -94,6 +94,7 @@ def _load():
         "vf_set_bvh_builder": ([P, I32], I32),
         "vf_set_bvh_leaf_size": ([P, I32], I32),
         "vf_set_spatial_order": ([P, I32], I32),
+        "vf_set_cost_order": ([P, I32], I32),
         "vf_set_timing": ([P, I32], I32),
         "vf_timing_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32], I32),
         "vf_closest_point": ([P, I64, P, P, I32, ctypes.c_float, P, P, P, P], I32),

@@ -18,7 +18,9 @@
 // tiles of one agent; the grid covers n agents x ceil(tiles(max_h, max_w) /
 // kWavesPerBlock) groups.  Workgroups are remapped so
 // each XCD (workgroup id mod 8) processes a contiguous range of agents, keeping
-// one agent's (and, with agents grouped by scene, one scene's) traffic in one L2.
+// one agent's (and, with agents grouped by scene, one scene's) traffic in one L2.  Within its range an
+// XCD may take the workgroups in an order given by k_group_order (longest packets first); every
+// wavefront reports its traversal work for the next launch's order.
 //
 // The fused kernel (vf_step with views) first advances the agent's dynamics in
 // one lane per workgroup (every workgroup of the agent computes the same bits),
@@ -88,7 +90,7 @@ template <int NR, bool STATS, int FIX, int SGN>
 __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&valid)[NR], const float o[3],
                                              const float (&d)[NR][3], float t_near, float t_far,
                                              float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
-                                             TraceStats& ts) {
+                                             TraceStats& ts, int32_t& work) {
     const Node CONST_AS* nodes = (const Node CONST_AS*)sc.nodes;
     const Tri CONST_AS* tris = (const Tri CONST_AS*)sc.tris;
     float inv[NR][3], oi[NR][3];
@@ -150,6 +152,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
 #pragma unroll
                 for (int i = kOrderWord; i < kNodeWords; ++i) asm volatile("" ::"s"(w[i]));
             }
+            work += 3;      // four box tests and the pushes: about three triangle tests' worth
             if (STATS) {
                 ts.node_wave += 1;
                 ts.node_lane += n_valid;
@@ -240,6 +243,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             // instead of many small ones
 #pragma unroll
             for (int j = 0; j < kLeafMax; ++j) asm volatile("" ::"s"(tw[12 * j + 7]), "s"(tw[12 * j + 11]));
+            work += cnt;
             if (STATS) {
                 ts.tri_wave += cnt;
                 ts.tri_lane += cnt * n_valid;
@@ -365,7 +369,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_wav
 k_render(RenderArgs a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
-    const int g = logical_group(a.total_groups);
+    int g = logical_group(a.total_groups);
+    if (a.group_order) g = a.group_order[g];
     const int la = g / a.groups_per_agent;
     const int group = g - la * a.groups_per_agent;
     const int agent = a.order ? a.order[la] : la;
@@ -430,6 +435,7 @@ k_render(RenderArgs a) {
     float t_best[NR];
     int32_t id_best[NR];
     TraceStats ts = {0, 0, 0, 0, 0, 0, 0};
+    int32_t work = 0;
     // one octant for every ray of the packet (lanes outside the image do not count: their best depth
     // of -1 fails every test)?  Then the traversal with the slab planes fixed at compile time.
     uint64_t m_neg[3] = {0, 0, 0}, m_pos[3] = {0, 0, 0};
@@ -451,7 +457,7 @@ k_render(RenderArgs a) {
     if (!VF_OCTANT_PACKETS) fix = 0;
     if (!VF_PARTIAL_OCTANT && fix != 7) fix = 0;
     if (__builtin_popcount(fix) < 2) fix = 0;       // two or three mixed axes: the general test
-#define VF_TRACE(F, S) trace_packet<NR, STATS, F, S>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts)
+#define VF_TRACE(F, S) trace_packet<NR, STATS, F, S>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts, work)
     switch (fix == 0 ? 0 : (fix << 3) | sgn) {
         case (7 << 3) | 0: VF_TRACE(7, 0); break;
         case (7 << 3) | 1: VF_TRACE(7, 1); break;
@@ -502,6 +508,8 @@ k_render(RenderArgs a) {
             }
         }
     }
+    if (a.cost && lane == 0)
+        a.cost[(int64_t)g * kWavesPerBlock + wave] = work;
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
         unsigned long long v[7] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
@@ -646,11 +654,70 @@ hipError_t launch_order(const OrderArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Cost order of a launch's workgroups: the render hands the hardware workgroup ids in turn to the eight
+// XCDs, and each XCD takes its contiguous range of logical groups in order (the remap above).  Within each
+// XCD's range the groups are put in decreasing order of the traversal work their wavefronts reported in
+// the previous launch of the same shape (a counting sort over 32 buckets, two per octave; one workgroup
+// per XCD range), so long packets start first and short ones fill the end of the launch instead of a few
+// long ones running alone.  Work is kept per logical group, so a change of the agents' spatial order
+// between launches only makes the estimate staler.  Any cost values, stale or uninitialised, give a valid
+// permutation of each range: the bucket of every group is computed once and kept in LDS for both passes.
+// The order changes which workgroup renders a packet, never what it renders.
+__device__ __forceinline__ int cost_bucket(uint32_t c) {
+    // two buckets per octave of c + 1, largest first
+    const uint32_t v = c < 0xFFFFFFFFu ? c + 1u : c;
+    const int lg = 31 - __clz(v);
+    const int half = lg > 0 ? (int)((v >> (lg - 1)) & 1u) : 0;
+    const int b = 2 * lg + half;
+    return kCostBuckets - 1 - (b < kCostBuckets - 1 ? b : kCostBuckets - 1);
+}
+
+__global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) {
+    __shared__ uint8_t bucket[kGroupOrderMax / 8];
+    __shared__ int32_t off[kCostBuckets];
+    const int t = threadIdx.x, x = blockIdx.x;
+    const int q = a.total >> 3, r = a.total & 7;
+    const int begin = x * q + (x < r ? x : r), size = q + (x < r ? 1 : 0);
+    if (t < kCostBuckets) off[t] = 0;
+    __syncthreads();
+    for (int i = t; i < size; i += blockDim.x) {
+        uint32_t c = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            const uint32_t cw = (uint32_t)a.cost[(int64_t)(begin + i) * kWavesPerBlock + w];
+            c = c + cw < c ? 0xFFFFFFFFu : c + cw;
+        }
+        const int b = cost_bucket(c);
+        bucket[i] = (uint8_t)b;
+        atomicAdd(&off[b], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = begin;
+        for (int b = 0; b < kCostBuckets; ++b) {
+            const int c = off[b];
+            off[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < size; i += blockDim.x) a.perm[atomicAdd(&off[bucket[i]], 1)] = begin + i;
+}
+
+hipError_t launch_group_order(const GroupOrderArgs& a, hipStream_t st) {
+    if (a.total <= 0 || a.total > kGroupOrderMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_group_order, dim3(8), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+int32_t render_groups_per_agent(int32_t max_h, int32_t max_w) {
+    const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
+    int tiles = ((max_h + th - 1) / th) * ((max_w + tw - 1) / tw);
+    return (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
-    int tiles = ((a.max_h + th - 1) / th) * ((a.max_w + tw - 1) / tw);
-    a.groups_per_agent = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    a.groups_per_agent = render_groups_per_agent(a.max_h, a.max_w);
     int64_t total = (int64_t)a.n * a.groups_per_agent;
     if (total > 0x7fffffff) return hipErrorInvalidValue;
     a.total_groups = (int32_t)total;

@@ -201,7 +201,7 @@ vf_status vf_destroy(vf_ctx* ctx) {
     ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes);
     ctx_free(ctx, (void*)ctx->d_labels, sizeof(void*) * kMaxScenes);
     if (ctx->swarm_bytes) ctx_free(ctx, (void*)ctx->swarm.off, ctx->swarm_bytes);
-    for (auto& o : ctx->orders) ctx_free(ctx, o.second, kOrderMax * 4);
+    for (auto& o : ctx->orders) ctx_free(ctx, o.order, kStreamScratchBytes);
     for (auto* list : {&ctx->timing_events, &ctx->timing_free})
         for (auto& ev : *list) {
             (void)hipEventDestroy(ev.first);
@@ -329,29 +329,60 @@ static hipError_t timed_render(vf_ctx* ctx, const RenderArgs& a, bool fused, hip
     return e;
 }
 
-// Agent order scratch of a stream (one per stream, so concurrent streams never share it).
-static int32_t* order_for(vf_ctx* ctx, hipStream_t st) {
+// Launch-order scratch of a stream (one per stream, so concurrent streams never share it).
+static StreamScratch* scratch_for(vf_ctx* ctx, hipStream_t st) {
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         for (auto& o : ctx->orders)
-            if (o.first == (void*)st) return o.second;
+            if (o.stream == (void*)st) return &o;
     }
     void* p = nullptr;
-    if (ctx_alloc(ctx, &p, kOrderMax * 4) != VF_OK) return nullptr;
+    if (ctx_alloc(ctx, &p, kStreamScratchBytes) != VF_OK) return nullptr;
+    StreamScratch sc;
+    sc.stream = (void*)st;
+    sc.order = (int32_t*)p;
+    sc.cost = sc.order + kOrderMax;
+    sc.perm = sc.cost + (int64_t)kGroupOrderMax * kWavesPerBlock;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->orders.push_back({(void*)st, (int32_t*)p});
-    return (int32_t*)p;
+    ctx->orders.push_back(sc);
+    return &ctx->orders.back();
 }
 
-// Put a batch in spatial order before its render (batches of 64 .. kOrderAutoMax agents: at 1,024 the
-// rank-counting kernel takes 25 us and the render gains nothing measurable).
+// Launch order of a render: each XCD's workgroups longest first by the work the previous launch of the
+// same shape on this stream reported (launches of kGroupOrderMin .. kGroupOrderMax workgroups; the first
+// launch of a shape keeps the plain workgroup order and records the work).  Other batches of 64 ..
+// kOrderAutoMax agents are put in spatial order (at 1,024 agents the rank-counting kernel takes 25 us and
+// the render gains nothing measurable); the two are not combined: a cost-ordered launch gains nothing
+// from the spatial order, and its work estimates are kept per logical group, which the spatial order
+// would move between agents from one step to the next.
 static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
     a.order = nullptr;
-    if (!ctx->spatial_order || a.n < 64 || a.n > kOrderAutoMax) return;
-    int32_t* buf = order_for(ctx, st);
-    if (!buf) return;   // no memory for the scratch: identity order
-    OrderArgs o{a.n, a.env_idx, a.state, a.n_slots, a.views, buf};
-    if (launch_order(o, st) == hipSuccess) a.order = buf;
+    a.group_order = nullptr;
+    a.cost = nullptr;
+    const int32_t gpa = render_groups_per_agent(a.max_h, a.max_w);
+    const int64_t total = (int64_t)a.n * gpa;
+    const bool by_cost = ctx->cost_order && total >= kGroupOrderMin && total <= kGroupOrderMax;
+    const bool spatial = !by_cost && ctx->spatial_order && a.n >= 64 && a.n <= kOrderAutoMax;
+    if (!spatial && !by_cost) return;
+    StreamScratch* sc = scratch_for(ctx, st);
+    if (!sc) return;   // no memory for the scratch: plain order
+    if (spatial) {
+        OrderArgs o{a.n, a.env_idx, a.state, a.n_slots, a.views, sc->order};
+        if (launch_order(o, st) == hipSuccess) a.order = sc->order;
+    }
+    if (!by_cost) return;
+    bool have_cost;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        have_cost = sc->cost_n == a.n && sc->cost_groups == gpa;
+        sc->cost_n = a.n;
+        sc->cost_groups = gpa;
+    }
+    if (have_cost) {
+        GroupOrderArgs g{(int32_t)total, sc->cost, sc->perm};
+        if (launch_group_order(g, st) == hipSuccess) a.group_order = sc->perm;
+    }
+    a.cost = sc->cost;
 }
 
 static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_idx, float* state, int64_t n_slots,
@@ -630,6 +661,12 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
     for (int k = 0; k < 3; ++k) t.rgb[k] = rgb[k];
     ctx->swarm = t;
     ctx->swarm_bytes = bytes;
+    return VF_OK;
+}
+
+vf_status vf_set_cost_order(vf_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_cost_order: NULL context");
+    ctx->cost_order = enable != 0;
     return VF_OK;
 }
 

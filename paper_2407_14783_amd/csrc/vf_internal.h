@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <list>
 #include <mutex>
 #include <type_traits>
 #include <string>
@@ -29,6 +30,11 @@ constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
 #define VF_RENDER_WAVES 1
 #endif
 constexpr int kWavesPerBlock = VF_RENDER_WAVES;  // render workgroup = this many wavefronts, one packet each
+constexpr int kOrderMax = 1024;      // capacity of the spatial-order kernel (agents per batch)
+constexpr int kOrderAutoMax = 512;   // split launches of 64 .. this many agents are put in spatial order
+constexpr int kGroupOrderMax = 131072;  // capacity of the cost-order kernel (workgroups per launch)
+constexpr int kGroupOrderMin = 1024;    // smaller launches keep the plain order
+constexpr int kCostBuckets = 32;
 #ifndef VF_PACKET_ROWS
 #define VF_PACKET_ROWS 1
 #endif
@@ -178,6 +184,20 @@ struct Counters {               // per state buffer arrival counters of the fuse
 
 }  // namespace vf
 
+namespace vf {
+// Launch-order scratch of one stream: the agent order, the per-packet work its last render reported and
+// the workgroup order computed from it.  Only launches on that stream touch it.
+struct StreamScratch {
+    void* stream = nullptr;
+    int32_t* order = nullptr;     // [kOrderMax]
+    int32_t* cost = nullptr;      // [kGroupOrderMax * waves per workgroup]
+    int32_t* perm = nullptr;      // [kGroupOrderMax]
+    int32_t cost_n = -1;          // launch shape the cost array holds (views, groups per view)
+    int32_t cost_groups = -1;
+};
+constexpr int64_t kStreamScratchBytes = 4 * (kOrderMax + (int64_t)kGroupOrderMax * (kWavesPerBlock + 1));
+}  // namespace vf
+
 struct vf_ctx {
     int device = 0;
     int n_cu = 0;
@@ -200,7 +220,8 @@ struct vf_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;   // recorded pairs
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_free;     // reusable pairs
     bool spatial_order = true;             // render agents in (scene, position) order
-    std::vector<std::pair<void*, int32_t*>> orders;   // per stream: [kOrderMax] agent order scratch
+    bool cost_order = true;                // start each XCD's longest packets first
+    std::list<vf::StreamScratch> orders;   // per stream: order scratch (stable addresses)
 };
 
 namespace vf {
@@ -227,11 +248,11 @@ struct RenderArgs {
     unsigned long long* stats;
     int32_t* counters;
     const int32_t* order;    // logical agent -> view index (spatial order), or NULL for identity
+    const int32_t* group_order;   // dispatch position -> logical group (cost order), or NULL for identity
+    int32_t* cost;                // per (logical group, wavefront) traversal work written by the launch, or NULL
     SwarmTable swarm;
     DynConst dyn;
 };
-constexpr int kOrderMax = 1024;      // capacity of the spatial-order kernel (agents per batch)
-constexpr int kOrderAutoMax = 512;   // split launches of 64 .. this many agents are put in spatial order
 struct OrderArgs {
     int32_t n;
     const int32_t* env_idx;
@@ -241,6 +262,13 @@ struct OrderArgs {
     int32_t* order;
 };
 hipError_t launch_order(const OrderArgs& a, hipStream_t st);
+struct GroupOrderArgs {
+    int32_t total;               // workgroups of the launch
+    const int32_t* cost;         // [logical group][waves per workgroup] from the previous launch
+    int32_t* perm;               // out: [total], dispatch position -> logical group
+};
+hipError_t launch_group_order(const GroupOrderArgs& a, hipStream_t st);
+int32_t render_groups_per_agent(int32_t max_h, int32_t max_w);
 struct StepArgs {
     int32_t n;
     const int32_t* env_idx;

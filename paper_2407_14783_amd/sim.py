@@ -275,6 +275,11 @@ class Context:
         """Sort split-launch batches by (scene, position) before rendering (default on)."""
         check(lib.vf_set_spatial_order(self.h, 1 if on else 0), "vf_set_spatial_order")
 
+    def set_cost_order(self, on):
+        """Start each XCD's longest packets first, by the work the previous launch of the same shape
+        reported (default on)."""
+        check(lib.vf_set_cost_order(self.h, 1 if on else 0), "vf_set_cost_order")
+
     def set_timing(self, on):
         """Record HIP events around every render-kernel launch (see timing_read)."""
         check(lib.vf_set_timing(self.h, 1 if on else 0), "vf_set_timing")

@@ -422,6 +422,7 @@ def test_spatial_order_changes_nothing(vf):
     env_t = torch.as_tensor(env).cuda()
     outs = []
     header("spatial order on/off: 300 agents, 2 scenes")
+    ctx.set_cost_order(False)       # launches put in cost order skip the spatial order
     for on in (True, False):
         ctx.set_spatial_order(on)
         ctx.set_launch_mode(False)
@@ -436,6 +437,7 @@ def test_spatial_order_changes_nothing(vf):
         ctx.sync_check()
         outs.append([t.cpu().numpy() for t in (st, depth, ids, rgb, d2)])
     ctx.set_spatial_order(True)
+    ctx.set_cost_order(True)
     ctx.set_launch_mode(None)
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b, equal_nan=False)
@@ -448,6 +450,54 @@ def test_spatial_order_changes_nothing(vf):
         compare_render(outs[0][1][px], outs[0][2][px], None, ref, 100.0, f"agent {a}")
     for sid in sids:
         ctx.free_scene(sid)
+
+
+def test_cost_order_changes_nothing(vf):
+    """Longest-first workgroup order (from the work the previous launch of the same shape reported)
+    moves packets between workgroups only: repeated renders with it on and off, with launches of other
+    shapes in between and one too large for the order kernel (134,400 workgroups), are bitwise equal and
+    write every pixel."""
+    sim, ctx = vf
+    p = default_params()
+    sc = scenes.forest(seed=3, n_trees=300)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    rng = np.random.default_rng(78)
+    outs = {}
+    header("cost order on/off: 300, 120 and 2,100 agents, mixed sizes")
+    for n in (300, 120, 2100):
+        s0 = _dev(agents.forest_starts(10 + n, n, sc, p))
+        hw = np.array([(64, 64), (40, 24)])[rng.integers(0, 2, n)]
+        hw[0] = (64, 64)
+        views, npx, offs, mh, mw = sim.make_views(n, sid, hw)
+        for on in (True, False):
+            ctx.set_cost_order(on)
+            runs = []
+            for rep in range(3):
+                depth = torch.full((npx,), float("nan")).cuda()
+                ids = torch.full((npx,), -7, dtype=torch.int32).cuda()
+                ctx.render(s0, views, n=n, max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+                if n == 300 and rep == 1:
+                    # a launch of another shape on the same stream between two of the same shape
+                    d_small = torch.empty(20 * 64 * 64, device="cuda")
+                    v20, _, _, _, _ = sim.make_views(20, sid, (64, 64))
+                    ctx.render(s0, v20, n=20, max_hw=(64, 64), depth=d_small, out_pixels=20 * 64 * 64)
+                ctx.sync_check()
+                runs.append((depth.cpu().numpy(), ids.cpu().numpy()))
+            outs[(n, on)] = runs
+        ctx.set_cost_order(True)
+        ref_d, ref_i = outs[(n, False)][0]
+        assert not np.isnan(ref_d).any() and not (ref_i == -7).any()
+        for on in (True, False):
+            for d_, i_ in outs[(n, on)]:
+                assert np.array_equal(d_, ref_d) and np.array_equal(i_, ref_i), f"n={n} cost order {on}"
+        # spot-check against the oracle
+        st_np = s0.cpu().numpy()
+        for a in (0, n // 2):
+            h, w = hw[a]
+            ref = oren.render_view(st_np[a].astype(np.float64), sc, h, w, math.pi / 2)
+            px = slice(offs[a], offs[a] + h * w)
+            compare_render(ref_d[px], ref_i[px], None, ref, 100.0, f"n={n} agent {a}")
+    ctx.free_scene(sid)
 
 
 # ---------------------------------------------------------------------------
