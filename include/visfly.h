@@ -321,11 +321,11 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
  * changes which workgroup renders an agent, never the results. */
 vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
 
-/* Workgroup order of split launches of 1,024 .. 32,768 packets (vf_step split form, vf_render): with
+/* Workgroup order of split launches of 1,024 .. 262,144 packets (vf_step split form, vf_render): with
  * enable != 0 (the default) each render records the traversal work of every packet in per-stream scratch,
  * and the next launch on that stream with the same number of views and packets per view first runs one
- * small kernel that puts each XCD's workgroups in decreasing order of that work, so the longest packets
- * start first instead of running alone at the end of the launch.  The first launch of a shape keeps the
+ * small kernel that puts each XCD's workgroups in decreasing order of that work (in chunks of 16,384), so
+ * the longest packets start first instead of running alone at the end of the launch.  The first launch of a shape keeps the
  * plain order.  The order changes which workgroup renders a packet, never the results. */
 vf_status vf_set_cost_order(vf_ctx* ctx, int32_t enable);
 

@@ -657,9 +657,9 @@ hipError_t launch_order(const OrderArgs& a, hipStream_t st) {
 // Cost order of a launch's workgroups: the render hands the hardware workgroup ids in turn to the eight
 // XCDs, and each XCD takes its contiguous range of logical groups in order (the remap above).  Within each
 // XCD's range the groups are put in decreasing order of the traversal work their wavefronts reported in
-// the previous launch of the same shape (a counting sort over 32 buckets, two per octave; one workgroup
-// per XCD range), so long packets start first and short ones fill the end of the launch instead of a few
-// long ones running alone.  Work is kept per logical group, so a change of the agents' spatial order
+// the previous launch of the same shape (a counting sort over 32 buckets, two per octave, in chunks of
+// kGroupOrderChunk groups: one workgroup per chunk), so long packets start first and short ones fill the
+// end of the launch instead of a few long ones running alone.  Work is kept per logical group, so a change of the agents' spatial order
 // between launches only makes the estimate staler.  Any cost values, stale or uninitialised, give a valid
 // permutation of each range: the bucket of every group is computed once and kept in LDS for both passes.
 // The order changes which workgroup renders a packet, never what it renders.
@@ -673,11 +673,14 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
 }
 
 __global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) {
-    __shared__ uint8_t bucket[kGroupOrderMax / 8];
+    __shared__ uint8_t bucket[kGroupOrderChunk];
     __shared__ int32_t off[kCostBuckets];
-    const int t = threadIdx.x, x = blockIdx.x;
+    const int t = threadIdx.x, x = blockIdx.x & 7, chunk = blockIdx.x >> 3;
     const int q = a.total >> 3, r = a.total & 7;
-    const int begin = x * q + (x < r ? x : r), size = q + (x < r ? 1 : 0);
+    const int range = q + (x < r ? 1 : 0);
+    const int begin = x * q + (x < r ? x : r) + chunk * kGroupOrderChunk;
+    const int left = range - chunk * kGroupOrderChunk;
+    const int size = left < kGroupOrderChunk ? left : kGroupOrderChunk;      // <= 0: nothing to sort
     if (t < kCostBuckets) off[t] = 0;
     __syncthreads();
     for (int i = t; i < size; i += blockDim.x) {
@@ -705,7 +708,9 @@ __global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) {
 
 hipError_t launch_group_order(const GroupOrderArgs& a, hipStream_t st) {
     if (a.total <= 0 || a.total > kGroupOrderMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_group_order, dim3(8), dim3(1024), 0, st, a);
+    const int range = (a.total + 7) / 8;     // the largest XCD range
+    const int chunks = (range + kGroupOrderChunk - 1) / kGroupOrderChunk;
+    hipLaunchKernelGGL(k_group_order, dim3(8 * chunks), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 

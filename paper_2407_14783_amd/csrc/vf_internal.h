@@ -32,7 +32,8 @@ constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
 constexpr int kWavesPerBlock = VF_RENDER_WAVES;  // render workgroup = this many wavefronts, one packet each
 constexpr int kOrderMax = 1024;      // capacity of the spatial-order kernel (agents per batch)
 constexpr int kOrderAutoMax = 512;   // split launches of 64 .. this many agents are put in spatial order
-constexpr int kGroupOrderMax = 131072;  // capacity of the cost-order kernel (workgroups per launch)
+constexpr int kGroupOrderMax = 1 << 18;  // capacity of the cost-order kernel (workgroups per launch)
+constexpr int kGroupOrderChunk = 16384; // groups one workgroup of that kernel sorts
 constexpr int kGroupOrderMin = 1024;    // smaller launches keep the plain order
 constexpr int kCostBuckets = 32;
 #ifndef VF_PACKET_ROWS

@@ -455,19 +455,22 @@ def test_spatial_order_changes_nothing(vf):
 def test_cost_order_changes_nothing(vf):
     """Longest-first workgroup order (from the work the previous launch of the same shape reported)
     moves packets between workgroups only: repeated renders with it on and off, with launches of other
-    shapes in between and one too large for the order kernel (134,400 workgroups), are bitwise equal and
-    write every pixel."""
+    shapes in between, one sorted in two chunks per XCD and one too large for the order kernel (4,100 views
+    on a 128 x 128 grid: 1,049,600 workgroups), are bitwise equal and write every pixel."""
     sim, ctx = vf
     p = default_params()
     sc = scenes.forest(seed=3, n_trees=300)
     sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
     rng = np.random.default_rng(78)
     outs = {}
-    header("cost order on/off: 300, 120 and 2,100 agents, mixed sizes")
-    for n in (300, 120, 2100):
+    header("cost order on/off: 300, 120, 2,100 and 4,100 agents, mixed sizes")
+    for n in (300, 120, 2100, 4100):
         s0 = _dev(agents.forest_starts(10 + n, n, sc, p))
         hw = np.array([(64, 64), (40, 24)])[rng.integers(0, 2, n)]
         hw[0] = (64, 64)
+        if n == 4100:
+            hw[:] = (40, 24)
+            hw[0] = (128, 128)
         views, npx, offs, mh, mw = sim.make_views(n, sid, hw)
         for on in (True, False):
             ctx.set_cost_order(on)
@@ -492,7 +495,7 @@ def test_cost_order_changes_nothing(vf):
                 assert np.array_equal(d_, ref_d) and np.array_equal(i_, ref_i), f"n={n} cost order {on}"
         # spot-check against the oracle
         st_np = s0.cpu().numpy()
-        for a in (0, n // 2):
+        for a in (1, n // 2):
             h, w = hw[a]
             ref = oren.render_view(st_np[a].astype(np.float64), sc, h, w, math.pi / 2)
             px = slice(offs[a], offs[a] + h * w)
