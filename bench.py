@@ -4,7 +4,8 @@ A step is one vf_step call over the whole batch: CTBR controller, rotor lag,
 RK4 (Sec. III-A) and the 64x64 depth / triangle id / colour render of every
 agent at its new pose (Sec. III-B), on synthetic inputs resident in HBM.  The
 library picks the launch form (one fused kernel for small batches, else the
-dynamics kernel, the spatial-order kernel and the render kernel).
+dynamics kernel, an ordering kernel -- longest packets first by the previous
+step's traversal work, or agents in spatial order -- and the render kernel).
 
 Default workload ("forest-256"): 256 agents in a seeded procedural forest of
 2,000 open 32-segment cylinders on a 40 x 40 m ground quad (128,002 triangles),
