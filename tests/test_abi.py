@@ -51,3 +51,19 @@ def test_params_struct_roundtrip():
     s = capi.params_struct(p)
     raw = np.frombuffer(bytes(s), dtype=np.float32)
     assert np.isclose(raw[0], p["dt"]) and np.isclose(s.f_max, p["f_max"]) and list(s.k_rate) == [20.0, 20.0, 10.0]
+
+
+def test_option_setters_reject_a_null_context():
+    """Every option setter answers a NULL context with VF_EINVAL and a message naming itself, on the host
+    (no device call is made on that path)."""
+    from paper_2407_14783_amd import capi
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    lib.vf_last_error.restype = ctypes.c_char_p
+    lib.vf_last_error.argtypes = [ctypes.c_void_p]
+    for name in ("vf_set_spatial_order", "vf_set_cost_order", "vf_set_launch_mode", "vf_set_bvh_builder",
+                 "vf_set_bvh_leaf_size", "vf_set_stats", "vf_set_timing"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int32
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        assert fn(None, 1) == -1, name            # VF_EINVAL
+        assert name in lib.vf_last_error(None).decode(), name
