@@ -325,8 +325,11 @@ vf_status vf_set_spatial_order(vf_ctx* ctx, int32_t enable);
  * enable != 0 (the default) each render records the traversal work of every packet in per-stream scratch,
  * and the next launch on that stream with the same number of views and packets per view first runs one
  * small kernel that puts each XCD's workgroups in decreasing order of that work (in chunks of 16,384), so
- * the longest packets start first instead of running alone at the end of the launch.  The first launch of a shape keeps the
- * plain order.  The order changes which workgroup renders a packet, never the results. */
+ * the longest packets start first instead of running alone at the end of the launch.  The first launch
+ * of a shape keeps the plain order.  The scratch (about 2 MB per stream, charged to the context's budget)
+ * is allocated on a stream's first ordered launch and freed by vf_destroy; without memory for it the
+ * launch keeps the plain order.  The order changes which workgroup renders a packet, never the results.
+ * Returns VF_EINVAL for a NULL context. */
 vf_status vf_set_cost_order(vf_ctx* ctx, int32_t enable);
 
 /* How vf_step with views launches its work.  VF_LAUNCH_SPLIT: a dynamics
