@@ -447,8 +447,10 @@ vf_status vf_server_create(vf_ctx* ctx, const vf_server_config* cfg, float* stat
                            vf_server** out);
 /* env_slots [n_env] int32 [host], distinct, in [0, n_slots); actions [n_env][4] float32 [host];
  * out [host] or NULL (= host results only).  Returns at once with a ticket; VF_ENOSCENE /
- * VF_EINVAL / VF_ENOMEM (larger than one arena).  Device output buffers must stay valid until
- * the request completes. */
+ * VF_EINVAL (image size, hfov in (0, pi), 0 < near_clip < far_clip, slots) / VF_ENOMEM (larger
+ * than one arena).  Device output buffers must stay valid until the request completes.  Each
+ * batch has a device error word of its own: data a kernel of the batch had to skip fails that
+ * batch's requests with VF_EDEVICE (vf_server_wait), and never touches the context's word. */
 vf_status vf_server_submit(vf_server* s, const vf_request_desc* d, const int32_t* env_slots, const float* actions,
                            const vf_request_out* out, int64_t* ticket);
 /* done = 1 once the ticket's batch has completed. */

@@ -822,16 +822,14 @@ vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t
     VF_HIP(hipEventRecord(ev0, st));
 
     hipLaunchKernelGGL(k_tri_prep, dim3(nb_prep), dim3(kPrepThreads), 0, st, verts, nv, tris, nt, tlo, thi, cen,
-                       partial, ctx->d_err);
+                       partial, ctx->d_build_err);
     hipLaunchKernelGGL(k_reduce_bounds, dim3(1), dim3(kScanThreads), 0, st, partial, nb_prep, tlo, thi, nt, bounds);
     {
         // reject bad input before the passes that would work on it
         uint32_t bad = 0;
-        VF_HIP(hipMemcpyAsync(&bad, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        VF_HIP(hipMemcpyAsync(&bad, ctx->d_build_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         VF_HIP(hipStreamSynchronize(st));
         if (bad & (kErrTriIndex | kErrVertex)) {
-            const uint32_t zero = 0;
-            VF_HIP(hipMemcpy(ctx->d_err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice));
             return fail(VF_EINVAL, (bad & kErrTriIndex) ? "vf_scene_build: triangle vertex index out of range"
                                                         : "vf_scene_build: vertex coordinates must be finite");
         }

@@ -483,11 +483,13 @@ k_render(RenderArgs a) {
     }
 #undef VF_TRACE
     if (vw.swarm != 0) trace_members<NR>(a, vw, slot, sc.n_tris, valid, o, d, t_best, id_best);
+    // depth goes to the view's own target when the caller gave a table of them, else at out_offset
+    float* const dbase = a.depth_views ? a.depth_views[agent] : (a.depth ? a.depth + vw.out_offset : nullptr);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         if (!valid[k]) continue;
         int64_t pix = vw.out_offset + (int64_t)row[k] * vw.W + col[k];
-        if (a.depth) a.depth[pix] = id_best[k] >= 0 ? t_best[k] : vw.miss_depth;
+        if (dbase) dbase[(int64_t)row[k] * vw.W + col[k]] = id_best[k] >= 0 ? t_best[k] : vw.miss_depth;
         if (a.tri_id) a.tri_id[pix] = id_best[k];
         if (a.rgb) {
             int64_t plane = (int64_t)vw.H * vw.W;

@@ -180,6 +180,7 @@ vf_status vf_create(int device, size_t hbm_budget_bytes, vf_ctx** out) {
     if (s != VF_OK) { ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes); delete ctx; return s; }
     ctx->d_err = (uint32_t*)p;
     ctx->d_stats = (unsigned long long*)((char*)p + 64);
+    ctx->d_build_err = (uint32_t*)((char*)p + 128);
     if (hipMemset(p, 0, 256) != hipSuccess || sync_scene_table(ctx) != VF_OK) {
         vf_destroy(ctx);
         return fail(VF_EHIP, "vf_create: device initialisation failed");
@@ -226,16 +227,16 @@ vf_status vf_scene_build(vf_ctx* ctx, const float* verts, int64_t V, const int32
         id = (int32_t)ctx->scenes.size() - 1;
     }
     hipStream_t st = (hipStream_t)stream;
-    uint32_t zero = 0;
-    VF_HIP(hipMemcpyAsync(ctx->d_err, &zero, 4, hipMemcpyHostToDevice, st));
+    // the build's input check reports into a word of its own; the shared sticky word is left alone
+    const uint32_t zero = 0;
+    VF_HIP(hipMemcpyAsync(ctx->d_build_err, &zero, 4, hipMemcpyHostToDevice, st));
     SceneHost sh;
     vf_status s = build_scene(ctx, verts, V, tris, (int32_t)T, tri_rgb, st, &sh);
     if (s != VF_OK) return s;
     uint32_t err = 0;
-    VF_HIP(hipMemcpy(&err, ctx->d_err, 4, hipMemcpyDeviceToHost));
+    VF_HIP(hipMemcpy(&err, ctx->d_build_err, 4, hipMemcpyDeviceToHost));
     if (err & kErrTriIndex) {
         ctx_free(ctx, sh.block, sh.bytes);
-        VF_HIP(hipMemcpy(ctx->d_err, &zero, 4, hipMemcpyHostToDevice));
         return fail(VF_EINVAL, "vf_scene_build: triangle vertex index out of range");
     }
     sh.used = true;

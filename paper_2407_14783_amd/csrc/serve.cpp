@@ -45,6 +45,7 @@ struct Request {
     Clock::time_point done_at;
     bool done = false;
     vf_status status = VF_OK;
+    std::string why;            // reason of a failed status
     // results (host)
     std::vector<float> depth;
     std::vector<int32_t> tri_id;
@@ -62,7 +63,9 @@ struct SlotArena {
     std::vector<Request*> reqs;
     std::vector<int64_t> px_off;   // per request: first pixel in the batch
     int64_t n_agents = 0, n_px = 0;
-    int64_t off_views = 0, off_idx = 0, off_act = 0, off_depth = 0, off_ids = 0, off_rgb = 0, off_state = 0;
+    // arena sections: error word | views | depth targets | env idx | actions | depth | ids | rgb | state echo
+    int64_t off_views = 0, off_targets = 0, off_idx = 0, off_act = 0, off_depth = 0, off_ids = 0, off_rgb = 0,
+            off_state = 0;
     int64_t host_res = 0;      // start of the results in the host arena
 };
 
@@ -95,18 +98,27 @@ static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 // Bytes a request needs in an arena (work list + outputs + state echo).
 static int64_t request_bytes(const vf_server_config& cfg, const vf_request_desc& d) {
     int64_t px = (int64_t)d.H * d.W * d.n_env;
-    int64_t b = (int64_t)d.n_env * ((int64_t)sizeof(vf_view) + 4 + 16 + 17 * 4);   // view, slot, action, state
+    // view, depth target, slot, action, state
+    int64_t b = (int64_t)d.n_env * ((int64_t)sizeof(vf_view) + 8 + 4 + 16 + 17 * 4);
     b += px * 4;                                  // depth
     if (cfg.want_tri_id) b += px * 4;
     if (cfg.want_rgb) b += px * 3;
-    return b + 7 * 256;                           // worst-case alignment of the seven arena sections
+    return b + 9 * 256;                           // the error word's section and the alignment of the eight others
+}
+
+// A depth-only server renders a request's depth straight into the device buffer it named, when it keeps no
+// host results and the buffer is 4-byte aligned.
+static bool renders_in_place(const vf_server* s, const Request* r) {
+    return !s->cfg.want_tri_id && !s->cfg.want_rgb && r->out.depth && !r->host &&
+           (uintptr_t)r->out.depth % 4 == 0;
 }
 
 static void launch_batch(vf_server* s, SlotArena& a) {
-    // lay out the arena: views | env idx | actions | depth | ids | rgb | state echo
+    // lay out the arena: error word | views | depth targets | env idx | actions | depth | ids | rgb | state echo
     int64_t n = a.n_agents, px = a.n_px;
-    a.off_views = 0;
-    a.off_idx = align_up(a.off_views + n * (int64_t)sizeof(vf_view), 256);
+    a.off_views = 256;
+    a.off_targets = align_up(a.off_views + n * (int64_t)sizeof(vf_view), 256);
+    a.off_idx = align_up(a.off_targets + n * 8, 256);
     a.off_act = align_up(a.off_idx + n * 4, 256);
     a.off_depth = align_up(a.off_act + n * 16, 256);
     a.off_ids = align_up(a.off_depth + px * 4, 256);
@@ -127,46 +139,28 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     }
     char* h = (char*)a.host;
     char* d = (char*)a.dev;
+    *(uint32_t*)h = 0;          // the batch's own error word, uploaded with the work list
     vf_view* hv = (vf_view*)(h + a.off_views);
+    float** ht = (float**)(h + a.off_targets);
     int32_t* hi = (int32_t*)(h + a.off_idx);
     float* ha = (float*)(h + a.off_act);
     // A depth-only batch renders a request that asked for a device depth buffer (and no host results)
-    // straight into that buffer, with no copy afterwards: every view's output offset then counts, in
-    // floats, from the lowest target address of the batch (the arena's depth section for the others),
-    // and the render's bound check spans up to the highest target's end.
-    std::vector<uintptr_t> target(a.reqs.size(), 0);
-    bool direct = !s->cfg.want_tri_id && !s->cfg.want_rgb;
-    uintptr_t base = 0;
-    int64_t span = 0;
-    if (direct) {
-        uintptr_t lo = UINTPTR_MAX, hi_end = 0;
-        int64_t p0 = 0;
-        for (size_t k = 0; k < a.reqs.size(); ++k) {
-            const Request* r = a.reqs[k];
-            const int64_t rpx = (int64_t)r->desc.H * r->desc.W * r->desc.n_env;
-            const uintptr_t t = (r->out.depth && !r->host) ? (uintptr_t)r->out.depth
-                                                           : (uintptr_t)(d + a.off_depth + 4 * p0);
-            if (t % 4 != 0) {
-                direct = false;
-                break;
-            }
-            target[k] = t;
-            lo = std::min(lo, t);
-            hi_end = std::max(hi_end, t + 4 * (uintptr_t)rpx);
-            p0 += rpx;
-        }
-        if (direct) {
-            base = lo;
-            span = (int64_t)((hi_end - lo) / 4);
-        }
-    }
+    // straight into that buffer, with no copy afterwards: the render writes each view's depth to the entry
+    // of a per-view target table (the view's own H x W block of the request's buffer, or of the arena's
+    // depth section for the other requests).  The table is built here from the request's own buffer and
+    // size, so every target lies inside the buffer its request named; ids and colours keep the arena
+    // offsets and the arena-sized bound check.
+    const bool direct = !s->cfg.want_tri_id && !s->cfg.want_rgb;
     int64_t agent = 0, pix = 0;
     a.px_off.clear();
     for (size_t k = 0; k < a.reqs.size(); ++k) {
         Request* r = a.reqs[k];
         a.px_off.push_back(pix);
-        const int64_t req_off = direct ? (int64_t)((target[k] - base) / 4) : pix;
+        const int64_t req_off = pix;
+        const bool in_place = renders_in_place(s, r);
         for (int32_t e = 0; e < r->desc.n_env; ++e) {
+            const int64_t view_px = (int64_t)r->desc.H * r->desc.W;
+            ht[agent] = in_place ? r->out.depth + (int64_t)e * view_px : (float*)(d + a.off_depth) + pix;
             vf_view& v = hv[agent];
             memset(&v, 0, sizeof(v));
             v.scene_id = r->desc.scene_id;
@@ -185,8 +179,9 @@ static void launch_batch(vf_server* s, SlotArena& a) {
         }
     }
     hipError_t e = hipMemcpyAsync(d, h, a.off_depth, hipMemcpyHostToDevice, a.stream);
+    uint32_t* d_err = (uint32_t*)d;
     StepArgs sa{(int32_t)n, (const int32_t*)(d + a.off_idx), s->state, s->n_slots, (const float*)(d + a.off_act),
-                s->ctx->d_err, s->dyn};
+                d_err, s->dyn};
     if (e == hipSuccess) e = launch_step(sa, a.stream);
     RenderArgs ra;
     memset(&ra, 0, sizeof(ra));
@@ -199,11 +194,12 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     ra.views = (const vf_view*)(d + a.off_views);
     ra.max_h = s->cfg.max_h;
     ra.max_w = s->cfg.max_w;
-    ra.depth = direct ? (float*)base : (float*)(d + a.off_depth);
+    ra.depth = (float*)(d + a.off_depth);
+    ra.depth_views = direct ? (float* const*)(d + a.off_targets) : nullptr;
     ra.tri_id = s->cfg.want_tri_id ? (int32_t*)(d + a.off_ids) : nullptr;
     ra.rgb = s->cfg.want_rgb ? (uint8_t*)(d + a.off_rgb) : nullptr;
-    ra.out_pixels = direct ? span : px;
-    ra.err = s->ctx->d_err;
+    ra.out_pixels = px;
+    ra.err = d_err;
     ra.stats = s->ctx->d_stats;
     ra.swarm = s->ctx->swarm;
     // no spatial order here: for the server's batches (mostly one or two requests) the ordering kernel
@@ -224,7 +220,7 @@ static void launch_batch(vf_server* s, SlotArena& a) {
         Request* r = a.reqs[k];
         any_host |= r->host;
         int64_t rpx = (int64_t)r->desc.H * r->desc.W * r->desc.n_env, p0 = a.px_off[k];
-        const bool written = direct && r->out.depth && !r->host;   // rendered in place
+        const bool written = renders_in_place(s, r);
         if (r->out.depth && !written && e == hipSuccess)
             e = hipMemcpyAsync(r->out.depth, d + a.off_depth + 4 * p0, rpx * 4, hipMemcpyDeviceToDevice, a.stream);
         if (r->out.tri_id && s->cfg.want_tri_id && e == hipSuccess)
@@ -238,6 +234,8 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     }
     if (e == hipSuccess && any_host)
         e = hipMemcpyAsync(h + a.off_depth, d + a.off_depth, end - a.off_depth, hipMemcpyDeviceToHost, a.stream);
+    // the batch's error word comes back with it (the upload has read the host word before, in stream order)
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, 4, hipMemcpyDeviceToHost, a.stream);
     if (e == hipSuccess) e = hipEventRecord(a.event, a.stream);
     if (e != hipSuccess) {
         s->worker_error = std::string("batch launch: ") + hipGetErrorString(e);
@@ -258,9 +256,22 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     if (n > s->max_batch) s->max_batch = n;
 }
 
+// Device error bits as text.
+static std::string device_error_text(uint32_t err) {
+    std::string m = "device reported:";
+    if (err & kErrScene) m += " bad scene id;";
+    if (err & kErrSlot) m += " env slot out of range;";
+    if (err & kErrPixels) m += " output pixels out of range;";
+    if (err & kErrView) m += " bad view;";
+    if (err & kErrStack) m += " traversal stack overflow;";
+    return m;
+}
+
 static void finish_batch(vf_server* s, SlotArena& a) {
     Clock::time_point now = Clock::now();
     char* h = (char*)a.host;
+    // a fault a kernel of this batch flagged (data it skipped) fails every request of the batch
+    const uint32_t err = *(const uint32_t*)h;
     const float* depth = (const float*)(h + a.off_depth);
     const int32_t* ids = (const int32_t*)(h + a.off_ids);
     const uint8_t* rgb = (const uint8_t*)(h + a.off_rgb);
@@ -277,6 +288,10 @@ static void finish_batch(vf_server* s, SlotArena& a) {
             r->state.assign(st + 17 * agent, st + 17 * (agent + r->desc.n_env));
         }
         agent += r->desc.n_env;
+        if (err) {
+            r->status = VF_EDEVICE;
+            r->why = device_error_text(err);
+        }
         r->done_at = now;
         r->done = true;
         for (int32_t sl : r->slots) s->busy_slots.erase(sl);
@@ -418,6 +433,8 @@ vf_status vf_server_submit(vf_server* s, const vf_request_desc* d, const int32_t
     if (d->H < 1 || d->W < 1 || d->H > s->cfg.max_h || d->W > s->cfg.max_w)
         return fail(VF_EINVAL, "vf_server_submit: image size outside the server's limits");
     if (!(d->hfov > 0.f && d->hfov < 3.1415926f)) return fail(VF_EINVAL, "vf_server_submit: bad hfov");
+    if (!(d->near_clip > 0.f && d->far_clip > d->near_clip))
+        return fail(VF_EINVAL, "vf_server_submit: need 0 < near_clip < far_clip");
     if (d->scene_id < 0 || d->scene_id >= (int32_t)s->ctx->scenes.size() || !s->ctx->scenes[d->scene_id].used)
         return fail(VF_ENOSCENE, "vf_server_submit: no such scene");
     if (request_bytes(s->cfg, *d) > s->arenas[0].bytes)
@@ -475,8 +492,9 @@ vf_status vf_server_wait(vf_server* s, int64_t ticket, float* depth, int32_t* tr
         if (state) memcpy(state, r->state.data(), r->state.size() * 4);
     }
     if (latency_s) *latency_s = std::chrono::duration<double>(r->done_at - r->arrival).count();
+    const std::string why = r->why;
     delete r;
-    if (st != VF_OK) return fail(st, "vf_server_wait: batch failed");
+    if (st != VF_OK) return fail(st, "vf_server_wait: batch failed" + (why.empty() ? std::string() : ": " + why));
     return VF_OK;
 }
 

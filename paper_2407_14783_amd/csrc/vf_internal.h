@@ -208,7 +208,9 @@ struct vf_ctx {
     std::vector<vf::SceneHost> scenes;
     vf::SceneDesc* d_scenes = nullptr;     // device scene table [kMaxScenes]
     const int32_t** d_labels = nullptr;    // device table of per-scene label arrays [kMaxScenes]
-    uint32_t* d_err = nullptr;             // sticky error word
+    uint32_t* d_err = nullptr;             // sticky error word of the calls that take a stream
+    uint32_t* d_build_err = nullptr;       // error word of vf_scene_build's input check (its own, so a build
+                                           // never clears a fault another stream has reported)
     unsigned long long* d_stats = nullptr; // 8 counters
     bool stats = false;
     int32_t launch_mode = VF_LAUNCH_AUTO;
@@ -242,6 +244,7 @@ struct RenderArgs {
     int32_t groups_per_agent;
     int32_t total_groups;
     float* depth;
+    float* const* depth_views;    // per view: the view's own H x W depth target (replaces depth), or NULL
     int32_t* tri_id;
     uint8_t* rgb;
     int64_t out_pixels;

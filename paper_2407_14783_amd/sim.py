@@ -20,8 +20,9 @@ def _ptr(t):
 
 
 def _check_views(views, n):
-    if views is not None and views.numel() * views.element_size() < 40 * n:
-        raise ValueError(f"views holds fewer than n = {n} entries")
+    """views must hold at least n vf_view records (72 bytes each)."""
+    if views is not None and views.numel() * views.element_size() < capi.VIEW_DTYPE.itemsize * n:
+        raise ValueError(f"views holds fewer than n = {n} entries of {capi.VIEW_DTYPE.itemsize} bytes")
 
 
 def _check_rows(t, n, cols, name):
