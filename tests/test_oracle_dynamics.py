@@ -244,3 +244,83 @@ def test_rk4_convergence_order(n_sub):
     e1 = np.abs(run(0.02, 20) - ref)[0, :13].max()
     e2 = np.abs(run(0.01, 40) - ref)[0, :13].max()
     assert 12.0 < e1 / e2 < 20.0
+
+
+# ---------------------------------------------------------------------------
+# quadratic drag (Eq. 2, the c_quad term, read as -c |v_B| v_B per body axis)
+# ---------------------------------------------------------------------------
+
+def _drag_run(p, s, steps):
+    out = [s.copy()]
+    for _ in range(steps):
+        s = dyn.step(s, np.zeros((1, 4)), p)
+        out.append(s.copy())
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("c", [0.05, 0.2])
+def test_quadratic_drag_vertical_fall_tanh(c):
+    """Level attitude, rotors off, no linear drag: a fall from rest obeys v' = -g + (c/m) v^2, so
+    v(t) = -sqrt(m g / c) tanh(t sqrt(g c / m)) and the speed approaches the terminal sqrt(m g / c).
+    RK4 follows it within its global error, which falls ~16x when the step halves."""
+    m = 1.0
+    g = 9.81
+    p = _p(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0), c_quad=(c, c, c), mass=m)
+    s0 = make_states([[0.0, 0.0, 100.0]], p, rotor=[[0, 0, 0, 0]], quat=yaw_quat([0.3])).astype(np.float64)
+    v_term = math.sqrt(m * g / c)
+    rate = math.sqrt(g * c / m)
+
+    def err(dt, steps):
+        pp = dict(p, dt=dt)
+        tr = _drag_run(pp, s0.copy(), steps)
+        t = np.arange(steps + 1) * dt
+        exact = -v_term * np.tanh(t * rate)
+        assert np.allclose(tr[:, 0, 7:9], 0.0, atol=1e-14)       # the fall stays vertical
+        return np.abs(tr[:, 0, 9] - exact).max(), tr
+    e1, tr = err(0.02, 400)
+    e2, _ = err(0.01, 800)
+    assert e1 < 1e-6 * v_term, f"RK4 error {e1:.3e}"
+    assert 12.0 < e1 / e2 < 20.0, f"error ratio {e1 / e2:.2f}"
+    # after 8 s (several time constants) the speed is within 1e-3 of the terminal speed
+    assert abs(-tr[-1, 0, 9] - v_term) < 1e-3 * v_term
+    # position: integral of v, -(v_term / rate) log cosh(rate t)
+    t_end = 400 * 0.02
+    z_exact = 100.0 - v_term / rate * math.log(math.cosh(rate * t_end))
+    assert abs(tr[-1, 0, 2] - z_exact) < 1e-5 * v_term * t_end
+
+
+@pytest.mark.parametrize("yaw,factor", [(0.0, 1.0), (math.pi / 4, 1.0 / math.sqrt(2.0))])
+def test_quadratic_drag_is_per_body_axis(yaw, factor):
+    """No gravity, rotors off, velocity v0 along world x: with yaw 0 the body x axis carries all of it and
+    v' = -(c/m) v^2; with yaw 45 deg it splits equally over body x and y, the two drag components
+    -c (v/sqrt2)|v/sqrt2| and +c (v/sqrt2)|v/sqrt2| turn back onto world x, and v' = -(c/(sqrt2 m)) v^2.
+    Either way v(t) = v0 / (1 + k v0 t) with k = factor c / m, and the motion stays on world x.
+    A transposed rotation, a dropped |v_B| or a sign slip breaks one of the two cases."""
+    c, m, v0 = 0.1, 0.8, 12.0
+    p = _p(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0), c_quad=(c, c, c), mass=m, g=0.0)
+    s = make_states([[0.0, 0.0, 0.0]], p, rotor=[[0, 0, 0, 0]], vel=[[v0, 0.0, 0.0]],
+                    quat=yaw_quat([yaw])).astype(np.float64)
+    tr = _drag_run(p, s, 200)
+    k = factor * c / m
+    t = np.arange(201) * p["dt"]
+    exact = v0 / (1.0 + k * v0 * t)
+    assert np.abs(tr[:, 0, 7] - exact).max() < 1e-6 * v0
+    # off-track velocity only from the float32 rounding of the yaw quaternion (a transposed rotation would
+    # turn the drag of the 45 degree case onto world y, at the scale of v0)
+    assert np.abs(tr[:, 0, 8:10]).max() < 1e-7 * v0
+    # position: x(t) = log(1 + k v0 t) / k
+    assert abs(tr[-1, 0, 0] - math.log(1 + k * v0 * t[-1]) / k) < 1e-5 * v0
+
+
+def test_quadratic_drag_anisotropic_coefficients():
+    """Drift along body y with c_quad = (0, c, 0) decelerates as v0 / (1 + (c/m) v0 t); the same drift
+    along body x feels no drag at all (its coefficient is 0): each body axis has its own coefficient."""
+    c, m = 0.3, 1.0
+    p = _p(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0), c_quad=(0.0, c, 0.0), mass=m, g=0.0)
+    rot90 = yaw_quat([math.pi / 2])        # body y = world -x, body x = world y
+    s = make_states([[0, 0, 0.0]], p, rotor=[[0, 0, 0, 0]], vel=[[-5.0, 3.0, 0.0]], quat=rot90).astype(np.float64)
+    tr = _drag_run(p, s, 100)
+    t = np.arange(101) * p["dt"]
+    v_by = 5.0 / (1 + c / m * 5.0 * t)      # speed along body y (world -x)
+    assert np.abs(-tr[:, 0, 7] - v_by).max() < 1e-6 * 5
+    assert np.allclose(tr[:, 0, 8], 3.0, atol=1e-12)     # world y = body x: no drag
