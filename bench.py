@@ -30,14 +30,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "64x64 depth frames/s per MI355X + % of HBM roofline; serving p50/p99 latency"
-# VALU lane-operations per test as issued by the traversal kernel:
-# box tests are priced by the kernel's counting variant: 11 VALU ops in a one-octant packet (6 fused slab
-# distances with the exit growth folded in, 4 min/max, 1 compare), 14 with one mixed axis, 18 in general
-# (6 fused slab distances, 10 min/max, 1 multiply for the exit growth, 1 compare)
+# Work per test, in VALU lane-operations.  The roofline prices each test at the algorithmic figure of a
+# ray-box slab test (14) and a Moller-Trumbore ray-triangle test (28).  Beside it, the prices of what the
+# kernel issues: box tests from the counting variant (11 VALU ops in a one-octant packet: 6 fused slab
+# distances with the exit growth folded in, 4 min/max, 1 compare; 14 with one mixed axis; 18 in general:
+# 6 fused slab distances, 10 min/max, 1 multiply for the exit growth, 1 compare) and triangle tests at 40
+# (as compiled: 28 mul/FMA for 2 cross, 4 dot, 3 scalings by 1/det and u+v, 3 subs, 1 reciprocal,
+# 5 compares -- the last a 64-bit (depth, id) compare --, 2 selects, 1 move).
+OPS_PER_BOX, OPS_PER_TRI = 14, 28
+ISSUED_OPS_PER_TRI = 40
 NODE_BYTES, TRI_BYTES = 128, 48   # one 4-wide node; one leaf triangle record
-OPS_PER_TRI = 40       # Moller-Trumbore as compiled: 28 mul/FMA (2 cross, 4 dot, 3 scalings by 1/det, u+v), 3 subs,
-                       # 1 reciprocal, 5 compares (the last a 64-bit (depth, id) compare), 2 selects, 1 move
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
+ALU_UNIT = "T lane-ops/s"
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -242,7 +246,7 @@ def box_room_latency(ctx, sim, params, steps=100):
             "frames_per_s": 1e6 / min(out["split_us_per_step"], out["fused_us_per_step"])}
 
 
-def multi_scene_throughput(ctx, sim, params, steps=20):
+def multi_scene_throughput(ctx, sim, params, steps=20, count=True):
     """4,096 agents over the 8 room-graph scenes (Dirichlet split), half 64x64 and half 128x128 depth."""
     import torch
     from workloads import agents, scenes
@@ -266,6 +270,7 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
     p = sim.capi.params_struct(params)
     for k in range(3):
         ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+    state_at_start = state.clone()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ctx.set_timing(True)
@@ -279,6 +284,16 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
     ctx.set_timing(False)
     render_s = render_ms / 1e3 / max(render_launches, 1)
     ms = e0.elapsed_time(e1) / steps
+    roof = rates = None
+    if count:
+        # the same steps from the same states with the counting kernel variant (not timed)
+        state.copy_(state_at_start)
+        ctx.read_stats(reset=True)
+        ctx.set_stats(True)
+        for k in range(steps):
+            ctx.step(p, state, acts[k], views=views, max_hw=(mh, mw), depth=depth, out_pixels=npx)
+        ctx.set_stats(False)
+        roof, rates = alu_roofline(ctx.read_stats(reset=True), steps, render_s)
     infos = [ctx.scene_info(s) for s in sids]
     for s in sids:
         ctx.free_scene(s)
@@ -291,6 +306,9 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
            "scene_build_device_ms": [round(float(i["build_ms"]), 2) for i in infos],
            "bvh_leaf_size": int(infos[0]["leaf_max"]),
            "scene_build_wall_s_incl_upload": build_s}
+    if roof:
+        out["alu_roofline"] = roof
+        out["test_rates"] = rates
     tk = committed_traffic("render_multiscene4096_pmc.md")
     if tk:
         traffic = (tk[0] + tk[1]) * 1024.0
@@ -298,6 +316,41 @@ def multi_scene_throughput(ctx, sim, params, steps=20):
                       "peak_GBps": HBM_PEAK_GBPS, "frac": traffic / render_s / 1e9 / HBM_PEAK_GBPS,
                       "source": "profiles/render_multiscene4096_pmc.md"}
     return out
+
+
+def alu_roofline(st, launches, render_s):
+    """ALU roofline of the render kernel from the counting replay's counters over `launches` launches and
+    the average launch time render_s (HIP events over the timed region).  achieved = the launch's ray-box
+    and ray-triangle tests priced at OPS_PER_BOX / OPS_PER_TRI, over render_s; beside it the same tests at
+    the kernel's issued prices, and the tests a lane's own ray asked for (per-ray traversal need)."""
+    rays = st["rays"] / launches
+    box, tri = st["box_lane"] / launches, st["tri_lane"] / launches
+    nbox, ntri = st["need_box"] / launches, st["need_tri"] / launches
+    ops = box * OPS_PER_BOX + tri * OPS_PER_TRI
+    issued_ops = st["box_ops"] / launches + tri * ISSUED_OPS_PER_TRI
+    need_ops = nbox * OPS_PER_BOX + ntri * OPS_PER_TRI
+    achieved = ops / render_s / 1e12
+    logical = st["node_wave"] / launches * NODE_BYTES + st["tri_wave"] / launches * TRI_BYTES
+    roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": ALU_UNIT,
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+            "prices": {"box_test": OPS_PER_BOX, "tri_test": OPS_PER_TRI},
+            "frac_at_issued_prices": issued_ops / render_s / 1e12 / ALU_PEAK_TOPS,
+            "frac_per_ray_need": need_ops / render_s / 1e12 / ALU_PEAK_TOPS,
+            "render_kernel_us": render_s * 1e6,
+            "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
+                           "wave_node_visits": st["node_wave"] / launches,
+                           "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
+                           "needed_box_tests_per_ray": nbox / max(rays, 1),
+                           "needed_tri_tests_per_ray": ntri / max(rays, 1),
+                           "packet_efficiency_box": nbox / max(box, 1), "packet_efficiency_tri": ntri / max(tri, 1),
+                           "issued_valu_ops_per_box_test": st["box_ops"] / max(st["box_lane"], 1),
+                           "valu_ops": ops, "issued_valu_ops": issued_ops, "logical_scene_bytes": logical}}
+    rates = {"ray_box_tests_per_s": box / render_s, "ray_tri_tests_per_s": tri / render_s,
+             "valu_ceiling_box_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_BOX,
+             "valu_ceiling_tri_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_TRI,
+             "logical_scene_GBps": logical / render_s / 1e9,
+             "basis": "per second of render-kernel time; ceilings = VALU peak / algorithmic ops per test"}
+    return roof, rates
 
 
 def copy_ceiling_gbps(reps=5):
@@ -368,7 +421,7 @@ def main():
     if args.multi_scene_only:
         from workloads import default_params
         ctx = sim.Context(0)
-        print(json.dumps({"multi_scene": multi_scene_throughput(ctx, sim, default_params())}))
+        print(json.dumps({"multi_scene": multi_scene_throughput(ctx, sim, default_params(), count=not args.no_stats)}))
         ctx.close()
         return
     from workloads import agents, default_params, scenes
@@ -455,28 +508,9 @@ def main():
         run(args.warmup, args.warmup + args.steps)
         ctx.set_stats(False)
         st = ctx.read_stats(reset=True)
-        box = st["box_lane"] / args.steps
-        tri = st["tri_lane"] / args.steps
-        box_ops_launch = st["box_ops"] / args.steps
-        ops = box_ops_launch + tri * OPS_PER_TRI
-        achieved = ops / render_s / 1e12
-        rays = st["rays"] / args.steps
-        box_ops = box_ops_launch / max(box, 1)
-        logical = st["node_wave"] / args.steps * NODE_BYTES + st["tri_wave"] / args.steps * TRI_BYTES
-        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
-                           "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                           "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
-                                          "wave_node_visits": st["node_wave"] / args.steps,
-                                          "box_tests_per_ray": box / max(rays, 1), "tri_tests_per_ray": tri / max(rays, 1),
-                                          "valu_ops_per_box_test": box_ops,
-                                          "valu_ops": ops, "logical_scene_bytes": logical}}
-        out["test_rates"] = {"ray_box_tests_per_s": box / render_s, "ray_tri_tests_per_s": tri / render_s,
-                             "valu_ceiling_box_tests_per_s": ALU_PEAK_TOPS * 1e12 / box_ops,
-                             "valu_ceiling_tri_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_TRI,
-                             "logical_scene_GBps": logical / render_s / 1e9,
-                             "basis": "per second of render-kernel time; ceilings = VALU peak / ops per test"}
-        out["ray_tri_tests_per_s"] = tri / (ms_per_step / 1e3)
-        out["rays_per_s"] = rays / (ms_per_step / 1e3)
+        out["roofline"], out["test_rates"] = alu_roofline(st, args.steps, render_s)
+        out["ray_tri_tests_per_s"] = out["roofline"]["per_launch"]["ray_tri_tests"] / (ms_per_step / 1e3)
+        out["rays_per_s"] = out["roofline"]["per_launch"]["rays"] / (ms_per_step / 1e3)
     tk = tuple(float(x) for x in args.traffic_kib.split(",")) if args.traffic_kib else committed_traffic()
     if tk:
         fetch_kib, write_kib = tk

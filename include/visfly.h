@@ -265,24 +265,47 @@ vf_status vf_collision(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const flo
  * Noise draws come from Philox4x32-10 keyed by (seed, views[i].flags, pixel,
  * stream): deterministic and independent of batch composition.
  * ------------------------------------------------------------------------- */
-enum { VF_NOISE_NONE = 0, VF_NOISE_NORMAL = 1, VF_NOISE_SPECKLE = 2, VF_NOISE_SALT_PEPPER = 3 };
+enum { VF_NOISE_NONE = 0, VF_NOISE_NORMAL = 1, VF_NOISE_SPECKLE = 2, VF_NOISE_SALT_PEPPER = 3, VF_NOISE_POISSON = 4 };
 
+/* Noise of the three image sensors (Table II names Normal, speckle, Poisson and salt & pepper noise;
+ * its parameters are not in the paper, so every model takes its own).  Misses keep their depth;
+ * colour noise acts on every pixel; label noise acts on labelled pixels (label >= 0). 64 bytes. */
 typedef struct vf_noise {
-    int32_t depth_model;  /* depth: NORMAL D + s n, SPECKLE D (1 + s n), SALT_PEPPER p/2 -> far, p/2 -> near */
-    float depth_sigma;
-    float depth_p;
-    int32_t rgb_model;    /* colour: NORMAL / SPECKLE per channel (rounded, clamped); SALT_PEPPER whole pixel */
+    int32_t depth_model;  /* NORMAL D + s n; SPECKLE D (1 + s n); SALT_PEPPER p/2 -> far, p/2 -> near;
+                             POISSON P(D c) / c, drawn in FP64 and rounded to float32 once */
+    float depth_sigma;    /* s (m for NORMAL, relative for SPECKLE), >= 0 */
+    float depth_p;        /* salt & pepper probability in [0, 1] */
+    float depth_scale;    /* c, Poisson counts per metre, > 0 when POISSON */
+    int32_t rgb_model;    /* per channel, rounded half up and clamped to [0, 255]: NORMAL v + s n,
+                             SPECKLE v (1 + s n), POISSON P(v c) / c; SALT_PEPPER sets the pixel to 255 / 0 */
     float rgb_sigma;      /* in 0..255 units for NORMAL */
     float rgb_p;
+    float rgb_scale;      /* c, Poisson counts per colour level */
+    int32_t seg_model;    /* labels: NORMAL l + floor(s n + 1/2); SPECKLE floor(l (1 + s n) + 1/2);
+                             POISSON floor(P(l c) / c + 1/2); SALT_PEPPER p/2 -> seg_salt_label, p/2 -> -1 */
+    float seg_sigma;
+    float seg_p;
+    float seg_scale;      /* c, Poisson counts per label unit */
+    int32_t seg_salt_label;
+    int32_t reserved;     /* must be 0 */
     uint64_t seed;
 } vf_noise;
 
-/* Apply noise in place to rendered depth [dev, nullable] and planar rgb [dev, nullable] of n
- * agents laid out by views [n] [dev].  tri_id [dev, nullable]: misses (id -1) keep their depth;
- * without ids every pixel is perturbed. */
+/* Apply noise in place to rendered depth, planar rgb and segmentation labels [dev, each nullable] of
+ * n agents laid out by views [n] [dev] (Sec. III-D, Table II).  tri_id [dev, nullable]: misses (id -1)
+ * keep their depth; without ids every depth pixel is perturbed.  Draws are keyed by (seed,
+ * views[i].flags, pixel, stream), so an agent's noise does not depend on the batch.  Bad models or
+ * parameters -> VF_EINVAL; bad views raise VF_EDEVICE at the next vf_sync_check. */
 vf_status vf_sensor_noise(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
-                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb,
+                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb, int32_t* seg,
                           int64_t out_pixels, void* stream);
+
+/* The same depth and colour noise applied by the render kernel itself, before its writes, in every
+ * later vf_step / vf_render of this context (a fused epilogue: no second pass over the images).  The
+ * result equals vf_render followed by vf_sensor_noise with the same configuration, bit for bit.
+ * noise is copied; NULL (or models NONE) turns it off.  The label fields are ignored (labels are not
+ * a render output).  The server's batches are not affected. */
+vf_status vf_set_render_noise(vf_ctx* ctx, const vf_noise* noise);
 
 /* Per-triangle semantic labels of a scene ([T] int32 [dev], copied; NULL removes them). */
 vf_status vf_scene_set_labels(vf_ctx* ctx, int32_t scene_id, const int32_t* labels);
@@ -368,12 +391,15 @@ vf_status vf_set_bvh_leaf_size(vf_ctx* ctx, int32_t max_tris);
 vf_status vf_set_stats(vf_ctx* ctx, int32_t enable);
 
 /* Read (and optionally reset) the counters: out[0] rays, out[1] inner-node
- * visits per lane, out[2] ray-box tests, out[3] ray-triangle tests,
- * out[4] wave-level node visits, out[5] wave-level triangle loads,
- * out[6] VALU operations of the box tests (11 per test in a packet whose rays share
- * one direction octant, 14 where they differ in the sign of one axis, 18 otherwise),
- * out[7] hits.  Synchronises the device. */
-vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset);
+ * visits per lane, out[2] ray-box tests, out[3] ray-triangle tests (1-3: issued, every
+ * valid lane at every node or leaf its packet visits), out[4] wave-level node visits,
+ * out[5] wave-level triangle loads, out[6] VALU operations of the box tests (11 per test
+ * in a packet whose rays share one direction octant, 14 where they differ in the sign of
+ * one axis, 18 otherwise), out[7] hits, out[8] node visits, out[9] ray-box tests and
+ * out[10] ray-triangle tests a lane's own ray asked for (visits of nodes and leaves whose
+ * box that ray entered), out[11] 0.  Synchronises the device. */
+#define VF_STAT_COUNT 12
+vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[VF_STAT_COUNT], int32_t reset);
 
 /* Render-kernel timing: while enabled (1), vf_step and vf_render record a pair of
  * HIP events on the caller's stream around every render-kernel launch.

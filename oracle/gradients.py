@@ -43,7 +43,7 @@ def central_difference(fun, x, direction, h=1e-6):
 
 
 def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_actions, h=1e-6, d0=1.0,
-                        w_goal=0.01, jump_abs=1e-2, jump_rel=1e-3):
+                        w_goal=0.01, jump_abs=1e-2, jump_rel=1e-3, return_jumps=False):
     """Directional derivative of the rollout loss along (u_state, u_actions) by central differences.
 
     Returns (derivative, smooth, corrected, n_jumps).  The loss is piecewise
@@ -53,7 +53,9 @@ def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_
     pixel jumped.  `corrected` removes exactly the jumped pixels' terms
     exp(-D/d0)/P from both rollouts before differencing: the derivative of the
     loss restricted to the pixels that stay on one smooth branch (a change of hit
-    triangle across a shared edge keeps the depth continuous and is kept).
+    triangle across a shared edge keeps the depth continuous and is kept).  With return_jumps the flags
+    of the removed pixel-steps come back too, [H, N, pixels] (step, agent, pixel), so that the gradient
+    being checked can be taken of the same restricted loss.
     """
     s0 = np.asarray(state0, dtype=np.float64)
     a = np.asarray(actions, dtype=np.float64)
@@ -63,12 +65,15 @@ def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_
                           return_images=True)
     raw = (lp - lm) / (2.0 * h)
     if dp.size == 0:
-        return raw, True, raw, 0
+        return (raw, True, raw, 0, np.zeros((0,), dtype=bool)) if return_jumps else (raw, True, raw, 0)
     jumped = np.abs(dp - dm) > jump_abs + jump_rel * np.minimum(np.abs(dp), np.abs(dm))
     n_pix = dp[0].size
     cp = float(np.sum(np.exp(-dp[jumped] / d0)) / n_pix)
     cm = float(np.sum(np.exp(-dm[jumped] / d0)) / n_pix)
     corrected = ((lp - cp) - (lm - cm)) / (2.0 * h)
+    if return_jumps:
+        n_agents = np.asarray(state0).shape[0]
+        return raw, not bool(jumped.any()), corrected, int(jumped.sum()), jumped.reshape(-1, n_agents, n_pix)
     return raw, not bool(jumped.any()), corrected, int(jumped.sum())
 
 

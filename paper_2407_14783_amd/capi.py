@@ -17,7 +17,7 @@ VF_RK4, VF_EULER = 0, 1
 VF_CTBR, VF_SRT, VF_PS, VF_LV = 0, 1, 2, 3
 VF_LAUNCH_SPLIT, VF_LAUNCH_FUSED, VF_LAUNCH_AUTO = 0, 1, 2
 VF_BVH_CLUSTER, VF_BVH_RADIX = 0, 1
-VF_NOISE_NONE, VF_NOISE_NORMAL, VF_NOISE_SPECKLE, VF_NOISE_SALT_PEPPER = 0, 1, 2, 3
+VF_NOISE_NONE, VF_NOISE_NORMAL, VF_NOISE_SPECKLE, VF_NOISE_SALT_PEPPER, VF_NOISE_POISSON = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "VF_OK", -1: "VF_EINVAL", -2: "VF_ENOMEM", -3: "VF_ENOSCENE", -4: "VF_EHIP", -5: "VF_EBUSY",
                 -6: "VF_EDEVICE"}
 
@@ -26,7 +26,8 @@ EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_sc
             "vf_step", "vf_render", "vf_step_backward", "vf_render_backward", "vf_set_stats", "vf_stats_read",
             "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_set_bvh_builder", "vf_set_bvh_leaf_size", "vf_server_create",
             "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
-            "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_cost_order", "vf_set_timing", "vf_timing_read")
+            "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_cost_order", "vf_set_timing", "vf_timing_read",
+            "vf_set_render_noise")
 
 
 class DynParams(ctypes.Structure):
@@ -40,7 +41,11 @@ class DynParams(ctypes.Structure):
 
 class Noise(ctypes.Structure):
     _fields_ = [("depth_model", ctypes.c_int32), ("depth_sigma", ctypes.c_float), ("depth_p", ctypes.c_float),
+                ("depth_scale", ctypes.c_float),
                 ("rgb_model", ctypes.c_int32), ("rgb_sigma", ctypes.c_float), ("rgb_p", ctypes.c_float),
+                ("rgb_scale", ctypes.c_float),
+                ("seg_model", ctypes.c_int32), ("seg_sigma", ctypes.c_float), ("seg_p", ctypes.c_float),
+                ("seg_scale", ctypes.c_float), ("seg_salt_label", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -64,7 +69,7 @@ TRI_DTYPE = np.dtype([("v0", "<f4", 3), ("id", "<i4"), ("e1", "<f4", 3), ("pad1"
                       ("pad2", "<f4")])
 assert VIEW_DTYPE.itemsize == 72 and NODE_DTYPE.itemsize == 128 and TRI_DTYPE.itemsize == 48
 assert NODE8_DTYPE.itemsize == 256
-assert ctypes.sizeof(DynParams) == 128 and ctypes.sizeof(Noise) == 32
+assert ctypes.sizeof(DynParams) == 128 and ctypes.sizeof(Noise) == 64
 
 
 class VfError(RuntimeError):
@@ -98,7 +103,8 @@ def _load():
         "vf_set_timing": ([P, I32], I32),
         "vf_timing_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32], I32),
         "vf_closest_point": ([P, I64, P, P, I32, ctypes.c_float, P, P, P, P], I32),
-        "vf_sensor_noise": ([P, I64, P, I32, I32, ctypes.POINTER(Noise), P, P, P, I64, P], I32),
+        "vf_sensor_noise": ([P, I64, P, I32, I32, ctypes.POINTER(Noise), P, P, P, P, I64, P], I32),
+        "vf_set_render_noise": ([P, ctypes.POINTER(Noise)], I32),
         "vf_scene_set_labels": ([P, I32, P], I32),
         "vf_set_swarms": ([P, I32, P, P, P, P], I32),
         "vf_collision": ([P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P, P, P], I32),

@@ -266,9 +266,9 @@ __device__ void substep_vjp(const DynConst& c, const float s[17], const float ac
     }
 }
 
-// One forward sub-step in place (same arithmetic as dyn_step's loop body).
-__device__ __forceinline__ void substep_fwd(const DynConst& c, float s[17], const float a[4]) {
-    DynConst one = c;
+// One forward sub-step in place (the step's own FP64 sub-step, its state rounded to float32).
+__device__ __forceinline__ void substep_fwd(const DynConstD& c, float s[17], const float a[4]) {
+    DynConstD one = c;
     one.n_sub = 1;
     dyn_step(one, s, a, s);
 }
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(128) k_step_backward(StepBackArgs a) {
     for (int sub = a.dyn.n_sub - 1; sub >= 0; --sub) {
         float s[17];
         for (int k = 0; k < 17; ++k) s[k] = s0[k];
-        for (int j = 0; j < sub; ++j) substep_fwd(a.dyn, s, act);
+        for (int j = 0; j < sub; ++j) substep_fwd(a.dynd, s, act);
         substep_vjp(a.dyn, s, act, lam, la);
     }
     for (int k = 0; k < 17; ++k) a.grad_in[(int64_t)i * 17 + k] = lam[k];

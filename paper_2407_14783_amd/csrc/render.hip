@@ -27,6 +27,7 @@
 // then renders at the new pose; the last workgroup of the agent to arrive on the
 // agent's counter writes the new state, so the state can be updated in place.
 #include "dynamics.h"
+#include "noise.h"
 #include "vf_internal.h"
 
 namespace vf {
@@ -59,8 +60,13 @@ __device__ __forceinline__ float safe_inv(float x) {
     return 1.0f / (fabsf(x) < eps ? copysignf(eps, x) : x);
 }
 
+// Counters of the counting variant.  *_lane: work issued per lane (every valid lane at every node and
+// leaf its packet visits); need_*: the part a lane's own ray asked for -- visits of nodes and leaves
+// whose box that ray entered (with its best depth at the time), the work a traversal of that ray alone
+// in the packet's order would do (with several rays per lane, a lane counts when any of them entered).
 struct TraceStats {
-    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_ops;
+    unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_ops, need_node, need_box,
+        need_tri;
 };
 
 // VALU operations of one ray-box test by the axes whose direction sign is fixed for the packet
@@ -136,6 +142,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
     int stk0 = 0, stk1 = 0;
     int sp = 0;
     int32_t entry = 0;          // root: inner node 0
+    // counting variant (one ray per lane): the lanes whose ray entered the entry being visited, kept
+    // beside the stack as two 32-bit halves per stack position
+    uint64_t act = __ballot(any);
+    uint32_t mlo0 = 0, mhi0 = 0, mlo1 = 0, mhi1 = 0;
+    uint64_t child_m[kWidth];
     while (true) {
         if (entry >= 0) {
             // the whole 128-byte node in one burst of wave-uniform (scalar) loads
@@ -158,6 +169,9 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 ts.node_lane += n_valid;
                 ts.box_lane += kWidth * n_valid;
                 ts.box_ops += (unsigned long long)box_test_ops(FIX) * kWidth * n_valid;
+                const unsigned mine = (unsigned)((act >> lane_id()) & 1ull) * (unsigned)n_valid;
+                ts.need_node += mine;
+                ts.need_box += kWidth * mine;
             }
             // bit k: some ray of the packet enters child k's box (empty slots hold a box no ray enters)
             uint32_t hb = 0;
@@ -194,6 +208,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     m |= __ballot(t0 <= fminf(t1, tb_box[r]));
                 }
                 hb |= (m != 0ull ? 1u : 0u) << k;
+                if (STATS) child_m[k] = m;
             }
             // the octant's child slots, near to far
             uint32_t slots;
@@ -226,6 +241,13 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                     // the depth limit of the build bounds sp below kStackCap
                     stk0 = lane_id() == sp ? e : stk0;
                     stk1 = lane_id() == sp - 64 ? e : stk1;
+                    if (STATS) {
+                        const uint64_t cm = child_m[k];
+                        mlo0 = lane_id() == sp ? (uint32_t)cm : mlo0;
+                        mhi0 = lane_id() == sp ? (uint32_t)(cm >> 32) : mhi0;
+                        mlo1 = lane_id() == sp - 64 ? (uint32_t)cm : mlo1;
+                        mhi1 = lane_id() == sp - 64 ? (uint32_t)(cm >> 32) : mhi1;
+                    }
                     ++sp;
                 }
             }
@@ -247,6 +269,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             if (STATS) {
                 ts.tri_wave += cnt;
                 ts.tri_lane += cnt * n_valid;
+                ts.need_tri += (unsigned)cnt * (unsigned)((act >> lane_id()) & 1ull) * (unsigned)n_valid;
             }
 #pragma unroll
             for (int j = 0; j < kLeafMax; ++j) {
@@ -297,6 +320,11 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
             const int32_t a0 = __builtin_amdgcn_readlane(stk0, sp & 63);
             const int32_t a1 = __builtin_amdgcn_readlane(stk1, sp & 63);
             entry = sp < 64 ? a0 : a1;
+            if (STATS) {
+                const uint32_t l0 = __builtin_amdgcn_readlane(mlo0, sp & 63), h0 = __builtin_amdgcn_readlane(mhi0, sp & 63);
+                const uint32_t l1 = __builtin_amdgcn_readlane(mlo1, sp & 63), h1 = __builtin_amdgcn_readlane(mhi1, sp & 63);
+                act = sp < 64 ? ((uint64_t)h0 << 32 | l0) : ((uint64_t)h1 << 32 | l1);
+            }
         }
     }
     if (STATS)
@@ -364,9 +392,8 @@ __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) 
     return true;
 }
 
-template <bool FUSED, bool STATS>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
-k_render(RenderArgs a) {
+template <bool FUSED, bool STATS, bool NOISE>
+__device__ __forceinline__ void render_body(const RenderArgs& a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
     int g = logical_group(a.total_groups);
@@ -434,7 +461,7 @@ k_render(RenderArgs a) {
     for (int k = 0; k < NR; ++k) pixel_ray(rot, tan_h, vw.H, vw.W, row[k], col[k], d[k]);
     float t_best[NR];
     int32_t id_best[NR];
-    TraceStats ts = {0, 0, 0, 0, 0, 0, 0};
+    TraceStats ts = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     int32_t work = 0;
     // one octant for every ray of the packet (lanes outside the image do not count: their best depth
     // of -1 fails every test)?  Then the traversal with the slab planes fixed at compile time.
@@ -488,38 +515,46 @@ k_render(RenderArgs a) {
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         if (!valid[k]) continue;
-        int64_t pix = vw.out_offset + (int64_t)row[k] * vw.W + col[k];
-        if (dbase) dbase[(int64_t)row[k] * vw.W + col[k]] = id_best[k] >= 0 ? t_best[k] : vw.miss_depth;
+        const int64_t in_view = (int64_t)row[k] * vw.W + col[k];
+        const int64_t pix = vw.out_offset + in_view;
+        if (dbase) {
+            float dv = id_best[k] >= 0 ? t_best[k] : vw.miss_depth;
+            // epilogue noise: the separate pass's function of the same pixel, so the same bits
+            if (NOISE && id_best[k] >= 0)
+                dv = noisy_depth_px(a.noise, (uint32_t)vw.flags, (uint32_t)in_view, dv, vw.near_clip, vw.far_clip);
+            dbase[in_view] = dv;
+        }
         if (a.tri_id) a.tri_id[pix] = id_best[k];
         if (a.rgb) {
-            int64_t plane = (int64_t)vw.H * vw.W;
-            uint8_t* dst = a.rgb + 3 * vw.out_offset + (int64_t)row[k] * vw.W + col[k];
+            const int64_t plane = (int64_t)vw.H * vw.W;
+            uint8_t* dst = a.rgb + 3 * vw.out_offset + in_view;
+            uint8_t ch[3] = {0, 0, 0};
             if (id_best[k] >= sc.n_tris) {
-                dst[0] = a.swarm.rgb[0];
-                dst[plane] = a.swarm.rgb[1];
-                dst[2 * plane] = a.swarm.rgb[2];
+                ch[0] = a.swarm.rgb[0];
+                ch[1] = a.swarm.rgb[1];
+                ch[2] = a.swarm.rgb[2];
             } else if (id_best[k] >= 0 && sc.rgb) {
                 const uint8_t* src = sc.rgb + 3 * (int64_t)id_best[k];
-                dst[0] = src[0];
-                dst[plane] = src[1];
-                dst[2 * plane] = src[2];
-            } else {
-                dst[0] = 0;
-                dst[plane] = 0;
-                dst[2 * plane] = 0;
+                ch[0] = src[0];
+                ch[1] = src[1];
+                ch[2] = src[2];
             }
+            if (NOISE) noisy_rgb_px(a.noise, (uint32_t)vw.flags, (uint32_t)in_view, ch);
+            dst[0] = ch[0];
+            dst[plane] = ch[1];
+            dst[2 * plane] = ch[2];
         }
     }
     if (a.cost && lane == 0)
         a.cost[(int64_t)g * kWavesPerBlock + wave] = work;
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
-        unsigned long long v[7] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
-                                   ts.box_ops};
+        unsigned long long v[10] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
+                                    ts.box_ops, ts.need_node, ts.need_box, ts.need_tri};
         unsigned long long rays = 0;
         for (int k = 0; k < NR; ++k) rays += valid[k] ? 1 : 0;
         for (int off = 32; off > 0; off >>= 1) {
-            for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], off);
+            for (int i = 0; i < 10; ++i) v[i] += __shfl_xor(v[i], off);
             rays += __shfl_xor(rays, off);
         }
         if (lane == 0) {
@@ -531,8 +566,26 @@ k_render(RenderArgs a) {
             atomicAdd(&a.stats[5], v[4] / 64);
             atomicAdd(&a.stats[6], v[6]);
             atomicAdd(&a.stats[7], v[5]);
+            atomicAdd(&a.stats[8], v[7]);
+            atomicAdd(&a.stats[9], v[8]);
+            atomicAdd(&a.stats[10], v[9]);
         }
     }
+}
+
+// The render kernel of split launches: occupancy of kRenderWavesPerEu waves per SIMD for the traversal.
+template <bool STATS, bool NOISE>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
+k_render(RenderArgs a) {
+    render_body<false, STATS, NOISE>(a);
+}
+
+// The fused kernel (small batches: few workgroups, so occupancy matters less than keeping the one-lane
+// FP64 dynamics and the traversal in registers): compiled for kFusedWavesPerEu waves per SIMD.
+template <bool STATS, bool NOISE>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEu)))
+k_render_fused(RenderArgs a) {
+    render_body<true, STATS, NOISE>(a);
 }
 
 __global__ void __launch_bounds__(256) k_step(StepArgs a) {
@@ -722,7 +775,22 @@ int32_t render_groups_per_agent(int32_t max_h, int32_t max_w) {
     return (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
 }
 
-hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st) {
+template <bool FUSED, bool STATS>
+static void launch_render_noise(bool noise, dim3 grid, dim3 block, hipStream_t st, const RenderArgs& a) {
+    if (FUSED) {
+        if (noise)
+            hipLaunchKernelGGL((k_render_fused<STATS, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_render_fused<STATS, false>), grid, block, 0, st, a);
+    } else {
+        if (noise)
+            hipLaunchKernelGGL((k_render<STATS, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_render<STATS, false>), grid, block, 0, st, a);
+    }
+}
+
+hipError_t launch_render(RenderArgs a, bool fused, bool stats, bool noise, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     a.groups_per_agent = render_groups_per_agent(a.max_h, a.max_w);
     int64_t total = (int64_t)a.n * a.groups_per_agent;
@@ -731,14 +799,14 @@ hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st) {
     dim3 grid((unsigned)total), block(64 * kWavesPerBlock);
     if (fused) {
         if (stats)
-            hipLaunchKernelGGL((k_render<true, true>), grid, block, 0, st, a);
+            launch_render_noise<true, true>(noise, grid, block, st, a);
         else
-            hipLaunchKernelGGL((k_render<true, false>), grid, block, 0, st, a);
+            launch_render_noise<true, false>(noise, grid, block, st, a);
     } else {
         if (stats)
-            hipLaunchKernelGGL((k_render<false, true>), grid, block, 0, st, a);
+            launch_render_noise<false, true>(noise, grid, block, st, a);
         else
-            hipLaunchKernelGGL((k_render<false, false>), grid, block, 0, st, a);
+            launch_render_noise<false, false>(noise, grid, block, st, a);
     }
     return hipGetLastError();
 }

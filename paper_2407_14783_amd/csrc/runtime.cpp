@@ -74,38 +74,59 @@ bool check_dyn_params(const vf_dyn_params& p, std::string* why) {
     return true;
 }
 
-DynConst make_dyn_const(const vf_dyn_params& p) {
-    DynConst c;
-    c.h = (float)((double)p.dt / (double)p.n_sub);
+template <typename T>
+static DynConstT<T> dyn_const(const vf_dyn_params& p) {
+    DynConstT<T> c;
+    const double h = (double)p.dt / (double)p.n_sub;
+    c.h = (T)h;
     c.n_sub = p.n_sub;
     c.integrator = p.integrator;
     c.ctrl = p.ctrl;
-    c.mass = p.mass;
-    c.inv_mass = (float)(1.0 / (double)p.mass);
-    c.g = p.g;
+    c.mass = (T)p.mass;
+    c.inv_mass = (T)(1.0 / (double)p.mass);
+    c.g = (T)p.g;
     for (int i = 0; i < 3; ++i) {
-        c.J[i] = p.J[i];
-        c.inv_J[i] = (float)(1.0 / (double)p.J[i]);
-        c.kJ[i] = (float)((double)p.J[i] * (double)p.k_rate[i]);
-        c.k_lin[i] = p.k_lin[i];
-        c.c_quad[i] = p.c_quad[i];
+        c.J[i] = (T)p.J[i];
+        c.inv_J[i] = (T)(1.0 / (double)p.J[i]);
+        c.kJ[i] = (T)((double)p.J[i] * (double)p.k_rate[i]);
+        c.k_lin[i] = (T)p.k_lin[i];
+        c.c_quad[i] = (T)p.c_quad[i];
     }
-    c.arm_a = (float)((double)p.arm / sqrt(2.0));
-    c.inv_a = (float)(sqrt(2.0) / (double)p.arm);
-    c.kappa = p.kappa_yaw;
-    c.inv_kappa = (float)(1.0 / (double)p.kappa_yaw);
-    c.f_max = p.f_max;
-    double h = (double)p.dt / (double)p.n_sub;
-    c.e_half = (float)exp(-0.5 * h / (double)p.tau_motor);
-    c.e_full = (float)exp(-h / (double)p.tau_motor);
+    c.arm_a = (T)((double)p.arm / sqrt(2.0));
+    c.inv_a = (T)(sqrt(2.0) / (double)p.arm);
+    c.kappa = (T)p.kappa_yaw;
+    c.inv_kappa = (T)(1.0 / (double)p.kappa_yaw);
+    c.f_max = (T)p.f_max;
+    c.e_half = (T)exp(-0.5 * h / (double)p.tau_motor);
+    c.e_full = (T)exp(-h / (double)p.tau_motor);
     for (int i = 0; i < 3; ++i) {
-        c.k_pos[i] = p.k_pos[i];
-        c.k_vel[i] = p.k_vel[i];
-        c.k_att[i] = p.k_att[i];
+        c.k_pos[i] = (T)p.k_pos[i];
+        c.k_vel[i] = (T)p.k_vel[i];
+        c.k_att[i] = (T)p.k_att[i];
     }
-    c.tan_tilt = (float)tan((double)p.max_tilt);
-    c.min_lift = (float)(0.25 * (double)p.g);
+    c.tan_tilt = (T)tan((double)p.max_tilt);
+    c.min_lift = (T)(0.25 * (double)p.g);
     return c;
+}
+
+DynConst make_dyn_const(const vf_dyn_params& p) { return dyn_const<float>(p); }
+DynConstD make_dyn_const_d(const vf_dyn_params& p) { return dyn_const<double>(p); }
+
+bool check_noise(const vf_noise& c, std::string* why) {
+    auto model_ok = [](int32_t m) { return m >= VF_NOISE_NONE && m <= VF_NOISE_POISSON; };
+    if (!model_ok(c.depth_model) || !model_ok(c.rgb_model) || !model_ok(c.seg_model))
+        return *why = "noise model must be one of VF_NOISE_NONE .. VF_NOISE_POISSON", false;
+    auto sig = [](float x) { return isfinite(x) && x >= 0.f; };
+    auto prob = [](float x) { return x >= 0.f && x <= 1.f; };
+    if (!sig(c.depth_sigma) || !sig(c.rgb_sigma) || !sig(c.seg_sigma))
+        return *why = "noise sigma must be finite and >= 0", false;
+    if (!prob(c.depth_p) || !prob(c.rgb_p) || !prob(c.seg_p)) return *why = "noise p must be in [0, 1]", false;
+    auto scale_ok = [](int32_t m, float c) { return m != VF_NOISE_POISSON || (isfinite(c) && c > 0.f); };
+    if (!scale_ok(c.depth_model, c.depth_scale) || !scale_ok(c.rgb_model, c.rgb_scale) ||
+        !scale_ok(c.seg_model, c.seg_scale))
+        return *why = "a Poisson model needs a finite scale > 0", false;
+    if (c.reserved != 0) return *why = "reserved must be 0", false;
+    return true;
 }
 
 static vf_status sync_scene_table(vf_ctx* ctx) {
@@ -179,8 +200,8 @@ vf_status vf_create(int device, size_t hbm_budget_bytes, vf_ctx** out) {
     s = ctx_alloc(ctx, &p, 256);
     if (s != VF_OK) { ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes); delete ctx; return s; }
     ctx->d_err = (uint32_t*)p;
-    ctx->d_stats = (unsigned long long*)((char*)p + 64);
-    ctx->d_build_err = (uint32_t*)((char*)p + 128);
+    ctx->d_stats = (unsigned long long*)((char*)p + 64);        // VF_STAT_COUNT counters
+    ctx->d_build_err = (uint32_t*)((char*)p + 192);
     if (hipMemset(p, 0, 256) != hipSuccess || sync_scene_table(ctx) != VF_OK) {
         vf_destroy(ctx);
         return fail(VF_EHIP, "vf_create: device initialisation failed");
@@ -307,7 +328,8 @@ static vf_status check_render_common(vf_ctx* ctx, int64_t n, const float* state,
 
 // Render launch, bracketed by a pair of events on the stream while timing is enabled.
 static hipError_t timed_render(vf_ctx* ctx, const RenderArgs& a, bool fused, hipStream_t st) {
-    if (!ctx->timing) return launch_render(a, fused, ctx->stats, st);
+    const bool noise = ctx->render_noise_on;
+    if (!ctx->timing) return launch_render(a, fused, ctx->stats, noise, st);
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -323,7 +345,7 @@ static hipError_t timed_render(vf_ctx* ctx, const RenderArgs& a, bool fused, hip
         if (e != hipSuccess) return e;
     }
     e = hipEventRecord(ev.first, st);
-    if (e == hipSuccess) e = launch_render(a, fused, ctx->stats, st);
+    if (e == hipSuccess) e = launch_render(a, fused, ctx->stats, noise, st);
     if (e == hipSuccess) e = hipEventRecord(ev.second, st);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->timing_events.push_back(ev);
@@ -407,6 +429,7 @@ static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_id
     a.err = ctx->d_err;
     a.stats = ctx->d_stats;
     a.swarm = ctx->swarm;
+    a.noise = ctx->render_noise;
     return a;
 }
 
@@ -423,7 +446,7 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    DynConst dc = make_dyn_const(*params);
+    DynConstD dc = make_dyn_const_d(*params);
     if (!views) {
         StepArgs a{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
         VF_HIP(launch_step(a, st));
@@ -484,7 +507,8 @@ vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, 
         return fail(VF_EINVAL, "vf_step_backward: the adjoint covers the CTBR and SRT controllers");
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
-    StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action, make_dyn_const(*params)};
+    StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action, make_dyn_const(*params),
+                   make_dyn_const_d(*params)};
     VF_HIP(launch_step_backward(a, (hipStream_t)stream));
     return VF_OK;
 }
@@ -507,22 +531,34 @@ vf_status vf_render_backward(vf_ctx* ctx, int64_t n, const float* state, const v
 }
 
 vf_status vf_sensor_noise(vf_ctx* ctx, int64_t n, const vf_view* views, int32_t max_h, int32_t max_w,
-                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb,
+                          const vf_noise* noise, const int32_t* tri_id, float* depth, uint8_t* rgb, int32_t* seg,
                           int64_t out_pixels, void* stream) {
     if (!ctx || !noise) return fail(VF_EINVAL, "vf_sensor_noise: NULL argument");
     if (n < 0 || n > (1 << 24)) return fail(VF_EINVAL, "vf_sensor_noise: n must be in [0, 2^24]");
     if (n > 0 && !views) return fail(VF_EINVAL, "vf_sensor_noise: views is NULL");
     if (max_h < 1 || max_w < 1 || max_h > kMaxImage || max_w > kMaxImage)
         return fail(VF_EINVAL, "vf_sensor_noise: max_h/max_w must be in [1, 1024]");
-    auto model_ok = [](int32_t m) { return m >= VF_NOISE_NONE && m <= VF_NOISE_SALT_PEPPER; };
-    if (!model_ok(noise->depth_model) || !model_ok(noise->rgb_model)) return fail(VF_EINVAL, "vf_sensor_noise: bad model");
-    if (!(noise->depth_sigma >= 0.f) || !(noise->rgb_sigma >= 0.f) || !(noise->depth_p >= 0.f && noise->depth_p <= 1.f) ||
-        !(noise->rgb_p >= 0.f && noise->rgb_p <= 1.f))
-        return fail(VF_EINVAL, "vf_sensor_noise: sigma must be >= 0 and p in [0, 1]");
+    if (out_pixels < 0) return fail(VF_EINVAL, "vf_sensor_noise: out_pixels must be >= 0");
+    std::string why;
+    if (!check_noise(*noise, &why)) return fail(VF_EINVAL, "vf_sensor_noise: " + why);
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
-    NoiseArgs a{(int32_t)n, views, max_h, max_w, 0, *noise, tri_id, depth, rgb, out_pixels, ctx->d_err};
+    NoiseArgs a{(int32_t)n, views, max_h, max_w, 0, *noise, tri_id, depth, rgb, seg, out_pixels, ctx->d_err};
     VF_HIP(launch_noise(a, (hipStream_t)stream));
+    return VF_OK;
+}
+
+vf_status vf_set_render_noise(vf_ctx* ctx, const vf_noise* noise) {
+    if (!ctx) return fail(VF_EINVAL, "vf_set_render_noise: NULL context");
+    if (!noise) {
+        ctx->render_noise_on = false;
+        ctx->render_noise = vf_noise{};
+        return VF_OK;
+    }
+    std::string why;
+    if (!check_noise(*noise, &why)) return fail(VF_EINVAL, "vf_set_render_noise: " + why);
+    ctx->render_noise = *noise;
+    ctx->render_noise_on = noise->depth_model != VF_NOISE_NONE || noise->rgb_model != VF_NOISE_NONE;
     return VF_OK;
 }
 
@@ -705,12 +741,12 @@ vf_status vf_set_stats(vf_ctx* ctx, int32_t enable) {
     return VF_OK;
 }
 
-vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[8], int32_t reset) {
+vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[VF_STAT_COUNT], int32_t reset) {
     if (!ctx || !out) return fail(VF_EINVAL, "vf_stats_read: NULL argument");
     VF_HIP(hipSetDevice(ctx->device));
     VF_HIP(hipDeviceSynchronize());
-    VF_HIP(hipMemcpy(out, ctx->d_stats, 64, hipMemcpyDeviceToHost));
-    if (reset) VF_HIP(hipMemset(ctx->d_stats, 0, 64));
+    VF_HIP(hipMemcpy(out, ctx->d_stats, 8 * VF_STAT_COUNT, hipMemcpyDeviceToHost));
+    if (reset) VF_HIP(hipMemset(ctx->d_stats, 0, 8 * VF_STAT_COUNT));
     return VF_OK;
 }
 

@@ -85,7 +85,7 @@ struct vf_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     int64_t next_ticket = 1;
-    vf::DynConst dyn{};
+    vf::DynConstD dyn{};
     // statistics
     int64_t n_batches = 0, n_agents = 0, n_requests = 0, max_batch = 0;
     std::string worker_error;
@@ -204,7 +204,7 @@ static void launch_batch(vf_server* s, SlotArena& a) {
     ra.swarm = s->ctx->swarm;
     // no spatial order here: for the server's batches (mostly one or two requests) the ordering kernel
     // cost more than the cache locality it bought
-    if (e == hipSuccess) e = launch_render(ra, false, false, a.stream);
+    if (e == hipSuccess) e = launch_render(ra, false, false, false, a.stream);
     // gather the new states of the batch's env slots with the render's view of them, when a request of
     // the batch takes states back (host results or a device state buffer)
     bool want_state = false;
@@ -392,7 +392,7 @@ vf_status vf_server_create(vf_ctx* ctx, const vf_server_config* cfg, float* stat
     s->cfg = *cfg;
     s->state = state_table;
     s->n_slots = n_slots;
-    s->dyn = make_dyn_const(cfg->params);
+    s->dyn = make_dyn_const_d(cfg->params);
     int64_t per = cfg->hbm_budget_bytes / cfg->n_streams / 256 * 256;
     s->arenas.resize(cfg->n_streams);
     vf_status st = VF_OK;

@@ -57,6 +57,7 @@ constexpr int kWidthBits = kWidth == 4 ? 2 : 3;      // bits of a child slot ind
 // waves per SIMD the render kernel is compiled for: the 8-wide node needs 64 scalar registers
 // for one node, which 8 waves per SIMD cannot hold besides the rest
 constexpr int kRenderWavesPerEu = kWidth == 4 ? 8 : 6;
+constexpr int kFusedWavesPerEu = 2;   // the fused step + render (small batches: at most 1,024 workgroups)
 constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
 // builds deeper than this are rejected: a packet keeps at most kWidth - 1 pending siblings per level
 constexpr int kMaxBvhDepth = kWidth == 4 ? 40 : 18;
@@ -132,27 +133,34 @@ static_assert(sizeof(SceneDesc) == 64, "scene table entry is 64 bytes");
 static_assert(sizeof(vf_scene_info) == 80, "vf_scene_info layout");
 static_assert(sizeof(vf_view) == 72, "view descriptor is 72 bytes");
 static_assert(sizeof(vf_dyn_params) == 128, "parameter block is 128 bytes");
-static_assert(sizeof(vf_noise) == 32, "noise block is 32 bytes");
+static_assert(sizeof(vf_noise) == 64, "noise block is 64 bytes");
 
 // ---------------------------------------------------------------------------
 // dynamics constants, derived once per call on the host
 // ---------------------------------------------------------------------------
-struct DynConst {
-    float h;              // sub-step length dt / n_sub
+// Dynamics constants derived on the host from vf_dyn_params (in double, then held in T): the forward step
+// runs on the double set, the adjoint's float32 linearisation and the IMU on the float set.
+template <typename T>
+struct DynConstT {
+    T h;                  // sub-step length dt / n_sub
     int32_t n_sub, integrator, ctrl;
-    float mass, inv_mass, g;
-    float J[3], inv_J[3];
-    float kJ[3];          // J * k_rate
-    float arm_a, inv_a;   // arm / sqrt(2) and its reciprocal
-    float kappa, inv_kappa, f_max;
-    float k_lin[3], c_quad[3];
-    float e_half, e_full; // exp(-h / (2 tau)), exp(-h / tau)
-    float k_pos[3], k_vel[3], k_att[3];
-    float tan_tilt, min_lift;   // tan(max_tilt), g / 4
+    T mass, inv_mass, g;
+    T J[3], inv_J[3];
+    T kJ[3];              // J * k_rate
+    T arm_a, inv_a;       // arm / sqrt(2) and its reciprocal
+    T kappa, inv_kappa, f_max;
+    T k_lin[3], c_quad[3];
+    T e_half, e_full;     // exp(-h / (2 tau)), exp(-h / tau)
+    T k_pos[3], k_vel[3], k_att[3];
+    T tan_tilt, min_lift; // tan(max_tilt), g / 4
 };
+using DynConst = DynConstT<float>;
+using DynConstD = DynConstT<double>;
 
 DynConst make_dyn_const(const vf_dyn_params& p);
+DynConstD make_dyn_const_d(const vf_dyn_params& p);
 bool check_dyn_params(const vf_dyn_params& p, std::string* why);
+bool check_noise(const vf_noise& c, std::string* why);
 
 // ---------------------------------------------------------------------------
 // context
@@ -225,6 +233,8 @@ struct vf_ctx {
     bool spatial_order = true;             // render agents in (scene, position) order
     bool cost_order = true;                // start each XCD's longest packets first
     std::list<vf::StreamScratch> orders;   // per stream: order scratch (stable addresses)
+    vf_noise render_noise{};               // depth / colour noise of the render epilogue
+    bool render_noise_on = false;
 };
 
 namespace vf {
@@ -255,7 +265,8 @@ struct RenderArgs {
     const int32_t* group_order;   // dispatch position -> logical group (cost order), or NULL for identity
     int32_t* cost;                // per (logical group, wavefront) traversal work written by the launch, or NULL
     SwarmTable swarm;
-    DynConst dyn;
+    DynConstD dyn;
+    vf_noise noise;               // depth / colour noise of the epilogue (read by the noise variant only)
 };
 struct OrderArgs {
     int32_t n;
@@ -280,7 +291,7 @@ struct StepArgs {
     int64_t n_slots;
     const float* action;
     uint32_t* err;
-    DynConst dyn;
+    DynConstD dyn;
 };
 struct StepBackArgs {
     int32_t n;
@@ -289,7 +300,8 @@ struct StepBackArgs {
     const float* grad_out;
     float* grad_in;
     float* grad_action;
-    DynConst dyn;
+    DynConst dyn;        // the adjoint linearises in float32
+    DynConstD dynd;      // forward sub-steps recomputed as the step computed them
 };
 struct RenderBackArgs {
     const SceneDesc* scenes;
@@ -313,6 +325,7 @@ struct NoiseArgs {
     const int32_t* tri_id;
     float* depth;
     uint8_t* rgb;
+    int32_t* seg;
     int64_t out_pixels;
     uint32_t* err;
 };
@@ -369,7 +382,7 @@ struct QueryArgs {
 };
 hipError_t launch_closest_point(const QueryArgs& q, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, hipStream_t st);
-hipError_t launch_render(RenderArgs a, bool fused, bool stats, hipStream_t st);
+hipError_t launch_render(RenderArgs a, bool fused, bool stats, bool noise, hipStream_t st);
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);
 hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st);
 hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n, float* out, hipStream_t st);

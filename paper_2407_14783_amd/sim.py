@@ -201,18 +201,35 @@ class Context:
                                 slots.ctypes.data_as(ctypes.c_void_p), half, col), "vf_set_swarms")
 
     # ---------------------------------------------------------------- sensors
-    def sensor_noise(self, views, n, max_hw, out_pixels, depth=None, rgb=None, tri_id=None,
-                     depth_model=capi.VF_NOISE_NONE, depth_sigma=0.0, depth_p=0.0, rgb_model=capi.VF_NOISE_NONE,
-                     rgb_sigma=0.0, rgb_p=0.0, seed=0, stream=None):
-        """Table II noise applied in place to rendered depth / planar rgb (keys from views' flags)."""
+    @staticmethod
+    def noise_config(depth_model=capi.VF_NOISE_NONE, depth_sigma=0.0, depth_p=0.0, depth_scale=1.0,
+                     rgb_model=capi.VF_NOISE_NONE, rgb_sigma=0.0, rgb_p=0.0, rgb_scale=1.0,
+                     seg_model=capi.VF_NOISE_NONE, seg_sigma=0.0, seg_p=0.0, seg_scale=1.0, seg_salt_label=0, seed=0):
+        """A vf_noise record (Table II models of the three image sensors)."""
+        return capi.Noise(int(depth_model), float(depth_sigma), float(depth_p), float(depth_scale), int(rgb_model),
+                          float(rgb_sigma), float(rgb_p), float(rgb_scale), int(seg_model), float(seg_sigma),
+                          float(seg_p), float(seg_scale), int(seg_salt_label), 0, int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+    def sensor_noise(self, views, n, max_hw, out_pixels, depth=None, rgb=None, tri_id=None, seg=None, stream=None,
+                     **cfg):
+        """Table II noise applied in place to rendered depth / planar rgb / labels (keys from views' flags);
+        cfg takes the keyword arguments of noise_config()."""
         _check_views(views, n)
-        for t, c, nm in ((depth, 1, "depth"), (rgb, 3, "rgb"), (tri_id, 1, "tri_id")):
+        for t, c, nm in ((depth, 1, "depth"), (rgb, 3, "rgb"), (tri_id, 1, "tri_id"), (seg, 1, "seg")):
             _check_rows(t, out_pixels, c, nm)
-        cfg = capi.Noise(int(depth_model), float(depth_sigma), float(depth_p), int(rgb_model), float(rgb_sigma),
-                         float(rgb_p), int(seed) & 0xFFFFFFFFFFFFFFFF)
-        check(lib.vf_sensor_noise(self.h, n, _ptr(views), int(max_hw[0]), int(max_hw[1]), ctypes.byref(cfg),
-                                  _ptr(tri_id), _ptr(depth), _ptr(rgb), int(out_pixels), _stream(stream)),
+        rec = self.noise_config(**cfg)
+        check(lib.vf_sensor_noise(self.h, n, _ptr(views), int(max_hw[0]), int(max_hw[1]), ctypes.byref(rec),
+                                  _ptr(tri_id), _ptr(depth), _ptr(rgb), _ptr(seg), int(out_pixels), _stream(stream)),
               "vf_sensor_noise")
+
+    def set_render_noise(self, **cfg):
+        """Depth / colour noise applied by the render kernel's epilogue in later step / render calls (no
+        arguments: off); cfg takes the keyword arguments of noise_config()."""
+        if not cfg:
+            check(lib.vf_set_render_noise(self.h, None), "vf_set_render_noise")
+            return
+        rec = self.noise_config(**cfg)
+        check(lib.vf_set_render_noise(self.h, ctypes.byref(rec)), "vf_set_render_noise")
 
     def set_labels(self, sid, labels):
         """Per-triangle int32 semantic labels of a scene (None removes them)."""
@@ -295,9 +312,10 @@ class Context:
         check(lib.vf_set_stats(self.h, 1 if on else 0), "vf_set_stats")
 
     def read_stats(self, reset=True):
-        out = (ctypes.c_uint64 * 8)()
+        out = (ctypes.c_uint64 * 12)()
         check(lib.vf_stats_read(self.h, out, 1 if reset else 0), "vf_stats_read")
-        keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_ops", "hits")
+        keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_ops", "hits",
+                "need_node", "need_box", "need_tri", "reserved")
         return dict(zip(keys, list(out)))
 
     def mem_usage(self):

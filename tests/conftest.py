@@ -17,3 +17,16 @@ def pytest_configure(config):
 def params():
     from workloads import default_params
     return default_params()
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """Measured parity figures (errors against their bounds, directions compared), one line each."""
+    try:
+        from tests.gpu_util import format_records
+    except ImportError:
+        return
+    lines = format_records()
+    if lines:
+        terminalreporter.write_sep("-", "parity records")
+        for line in lines:
+            terminalreporter.write_line(line)

@@ -7,8 +7,26 @@ DEPTH_RTOL = 1e-4     # depth tolerance off the edge/tie mask
 STATE_TOL = 1e-5      # |s_gpu - s_oracle| <= STATE_TOL * max(1, |s_oracle|) per component
 
 
+RECORDS = []          # (test, fields) of measured errors and bounds, printed in the terminal summary
+
+
 def header(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def record(name, **fields):
+    """Keep a measured figure (an error and its bound, a count) for the end-of-run summary, which pytest
+    prints even under -q; also echoed at once."""
+    RECORDS.append((name, fields))
+    print(f"[gpu-record] {name} " + " ".join(f"{k}={_fmt(v)}" for k, v in fields.items()), flush=True)
+
+
+def _fmt(v):
+    return f"{v:.3e}" if isinstance(v, float) else str(v)
+
+
+def format_records():
+    return [f"{name} " + " ".join(f"{k}={_fmt(v)}" for k, v in fields.items()) for name, fields in RECORDS]
 
 
 def compare_render(depth, tri_id, rgb, ref, miss_depth, label=""):

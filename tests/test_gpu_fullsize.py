@@ -17,7 +17,7 @@ import torch
 
 from oracle import dynamics as odyn
 from oracle import render as oren
-from workloads import agents, default_params, scenes
+from workloads import agents, default_params, device_params, scenes
 from tests.gpu_util import compare_render, header, state_close
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def test_forest256_benchmark_configuration_sampled(vf):
                  tri_id=ids, rgb=rgb, out_pixels=npx)
     ctx.sync_check()
     s1 = state.cpu().numpy()
-    ref = odyn.step(prev.astype(np.float64), acts[steps - 1], p)
+    ref = odyn.step(prev.astype(np.float64), acts[steps - 1], device_params(p))
     assert state_close(s1, ref) <= 1e-5
     d, i, c = depth.cpu().numpy(), ids.cpu().numpy(), rgb.cpu().numpy()
     rng = np.random.default_rng(21)
@@ -99,7 +99,7 @@ def test_multi_scene_4096_sampled(vf):
                  tri_id=ids, out_pixels=npx)
     ctx.sync_check()
     s1 = state.cpu().numpy()
-    assert state_close(s1, odyn.step(prev.astype(np.float64), acts[1], p)) <= 1e-5
+    assert state_close(s1, odyn.step(prev.astype(np.float64), acts[1], device_params(p))) <= 1e-5
     d, i = depth.cpu().numpy(), ids.cpu().numpy()
     rng = np.random.default_rng(22)
     masked = []

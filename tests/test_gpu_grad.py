@@ -5,9 +5,11 @@ oracle's central-difference Jacobians (h = 1e-6) at the same float32 inputs.
 vf_render_backward: sum_pixels g * d depth / d (p, q) against central
 differences of the oracle's brute-force depth, off the edge mask.
 Rollout: the checkpointed BPTT of the differentiable rollout against central
-differences of the oracle's rollout loss along seeded random directions
-(directions along which some pixel's depth jumps between the +h and -h
-rollouts -- a silhouette crossing -- are dropped).
+differences of the oracle's rollout loss, along 8 seeded random directions and
+per coordinate (actions at steps 0, 31, 63 and the start state).  Pixel-steps
+whose depth jumps between the +h and -h rollouts (a silhouette crossing) are
+removed from both sides: from the oracle's difference and from the loss the
+device gradient is taken of.
 """
 import math
 
@@ -19,7 +21,7 @@ from oracle import dynamics as odyn
 from oracle import gradients as ograd
 from oracle import render as oren
 from workloads import agents, default_params, scenes
-from tests.gpu_util import header
+from tests.gpu_util import header, record
 
 pytestmark = pytest.mark.gpu
 
@@ -40,19 +42,29 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-12))
 
 
-def _random_states(rng, n, p, rate=1.0):
+def _random_states(rng, n, p, rate=1.0, speed=1.5):
     q = rng.normal(size=(n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
-    return agents.make_states(rng.uniform(-5, 5, (n, 3)), p, quat=q, vel=rng.normal(scale=1.5, size=(n, 3)),
+    return agents.make_states(rng.uniform(-5, 5, (n, 3)), p, quat=q, vel=rng.normal(scale=speed, size=(n, 3)),
                               omega=rng.uniform(-rate, rate, (n, 3)),
                               rotor=np.sqrt(p["mass"] * p["g"] / 4) * rng.uniform(0.8, 1.2, (n, 4)))
 
 
-@pytest.mark.parametrize("variant", ["ctbr", "ctbr_saturating", "srt", "euler_nsub2", "rk4_nsub3"])
+@pytest.mark.parametrize("variant", ["ctbr", "ctbr_saturating", "srt", "euler_nsub2", "rk4_nsub3", "quad_drag",
+                                     "quad_drag_srt"])
 def test_step_backward_matches_fd_jacobian(vf, variant):
     sim, ctx = vf
-    rng = np.random.default_rng({"ctbr": 1, "ctbr_saturating": 2, "srt": 3, "euler_nsub2": 4, "rk4_nsub3": 5}[variant])
-    if variant == "srt":
+    rng = np.random.default_rng({"ctbr": 1, "ctbr_saturating": 2, "srt": 3, "euler_nsub2": 4, "rk4_nsub3": 5,
+                                 "quad_drag": 6, "quad_drag_srt": 7}[variant])
+    speed = 1.5
+    if variant == "quad_drag":
+        # Eq. 2 with both terms, at body speeds (about 7 m/s) where the quadratic term dominates
+        p = default_params(c_quad=(0.04, 0.06, 0.1))
+        speed = 4.0
+    elif variant == "quad_drag_srt":
+        p = default_params(ctrl=odyn.SRT, c_quad=(0.1, 0.1, 0.1), k_lin=(0.0, 0.0, 0.0))
+        speed = 4.0
+    elif variant == "srt":
         p = default_params(ctrl=odyn.SRT)
     elif variant == "euler_nsub2":
         p = default_params(integrator=odyn.EULER, n_sub=2)
@@ -61,8 +73,8 @@ def test_step_backward_matches_fd_jacobian(vf, variant):
     else:
         p = default_params()
     n = 32
-    s = _random_states(rng, n, p)
-    if variant == "srt":
+    s = _random_states(rng, n, p, speed=speed)
+    if variant in ("srt", "quad_drag_srt"):
         a = (p["mass"] * p["g"] / 4 * rng.uniform(0.7, 1.3, (n, 4))).astype(np.float32)
     elif variant == "ctbr_saturating":
         a = agents.random_actions(int(rng.integers(1 << 30)), 1, n, p)[0]
@@ -79,6 +91,9 @@ def test_step_backward_matches_fd_jacobian(vf, variant):
     ref_in = np.einsum("nij,ni->nj", js, lam.astype(np.float64))
     ref_a = np.einsum("nij,ni->nj", ja, lam.astype(np.float64))
     gi, ga = g_in.cpu().numpy(), g_a.cpu().numpy()
+    record(f"step_backward[{variant}]", state_rel=max(_rel(gi[i], ref_in[i]) for i in range(n)),
+           action_rel=max(_rel(ga[i], ref_a[i]) for i in range(n) if np.linalg.norm(ref_a[i]) > 1e-6),
+           bound=2e-4)
     for i in range(n):
         assert _rel(gi[i], ref_in[i]) <= 2e-4, f"{variant} agent {i}: state cotangent rel err {_rel(gi[i], ref_in[i]):.2e}"
         if np.linalg.norm(ref_a[i]) > 1e-6:
@@ -131,53 +146,142 @@ def _crop_forest(sc, centers, radius):
     return {"verts": sc["verts"], "tris": sc["tris"][tri_sel], "rgb": sc["rgb"][tri_sel]}
 
 
-@pytest.mark.parametrize("w_goal", [0.01, 0.0])
-def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
-    """Differentiable rollout: 4 agents in a forest, horizon 64, checkpoints every 8 steps, 64x64 depth."""
-    sim, ctx = vf
-    from paper_2407_14783_amd import autograd as vag
+BPTT_TOL = 1e-3        # relative, per direction and per coordinate
+N_DIRECTIONS = 8
+
+
+def _bptt_setup(agent=None):
+    """4 agents in a forest (or one of them in a crop around it alone), horizon 64, hover-range actions,
+    goals 12 m away: the differentiable workload's configuration on the FD-checkable scale."""
     p = default_params()
     full = scenes.forest(seed=3)
     n, H = 4, 64
     s0 = agents.forest_starts(8, n, full, p)
-    sc = _crop_forest(full, s0[:, 0:3], 6.0)
     rng = np.random.default_rng(8)
     acts = np.concatenate([rng.uniform(0.9, 1.15, (H, n, 1)) * p["g"], rng.uniform(-0.6, 0.6, (H, n, 3))],
                           axis=2).astype(np.float32)
     ang = rng.uniform(0, 2 * np.pi, n)
     goals = (s0[:, 0:3] + np.stack([12 * np.cos(ang), 12 * np.sin(ang), np.zeros(n)], 1)).astype(np.float32)
-    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    if agent is not None:
+        s0, acts, goals = s0[agent:agent + 1], acts[:, agent:agent + 1], goals[agent:agent + 1]
+    sc = _crop_forest(full, s0[:, 0:3], 6.0)
+    return p, sc, s0, acts, goals, rng
+
+
+def _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal, keep=None, d0=1.0):
+    """Loss and its gradient through the checkpointed BPTT (k = 8).  keep [H, N, 4096] (0/1) drops
+    pixel-steps from the depth term, as the oracle's jump-corrected differences do."""
+    H, n = acts.shape[0], acts.shape[1]
     views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
     s0_t = _dev(s0).requires_grad_(True)
     a_t = _dev(acts).requires_grad_(True)
-    header(f"BPTT: 4 agents x 64 steps, k = 8, w_goal = {w_goal}")
     states, depths = vag.rollout(ctx, p, s0_t, a_t, views, (mh, mw), npx, checkpoint_every=8)
-    d0 = 1.0
-    loss = torch.exp(-depths.double() / d0).view(H, n, 64 * 64).mean(dim=2).sum() + \
-        w_goal * ((states[:, :, 0:3].double() - _dev(goals).double()) ** 2).sum()
+    e = torch.exp(-depths.double() / d0).view(H, n, 64 * 64)
+    if keep is not None:
+        e = e * torch.as_tensor(keep, dtype=torch.float64).cuda()
+    loss = e.mean(dim=2).sum() + w_goal * ((states[:, :, 0:3].double() - _dev(goals).double()) ** 2).sum()
     loss.backward()
-    g_s0 = s0_t.grad.cpu().numpy().astype(np.float64)
-    g_a = a_t.grad.cpu().numpy().astype(np.float64)
-    view = {"H": 64, "W": 64, "hfov": math.pi / 2, "near": 0.01, "far": 100.0}
-    l_ref = ograd.rollout_loss(s0, acts, p, sc, goals, view, d0=d0, w_goal=w_goal)
-    assert abs(loss.item() - l_ref) <= 1e-4 * abs(l_ref)
-    checked = 0
-    for j in range(4):
+    return loss.item(), s0_t.grad.cpu().numpy().astype(np.float64), a_t.grad.cpu().numpy().astype(np.float64)
+
+
+VIEW64 = {"H": 64, "W": 64, "hfov": math.pi / 2, "near": 0.01, "far": 100.0}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("w_goal", [0.01, 0.0])
+def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
+    """Differentiable rollout: 4 agents in a forest, horizon 64, checkpoints every 8, 64x64 depth.  The
+    directional derivative along 8 seeded unit directions (start states and all actions) against FP64
+    central differences (h = 1e-6) of the oracle's rollout loss, within 1e-3 relative, every direction.
+    Pixel-steps whose depth jumps between the two oracle rollouts (a silhouette crossing) are removed
+    from both sides: the oracle's difference leaves out their terms and the device gradient is taken of
+    the loss without them."""
+    sim, ctx = vf
+    from paper_2407_14783_amd import autograd as vag
+    p, sc, s0, acts, goals, rng = _bptt_setup()
+    n, H = s0.shape[0], acts.shape[0]
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    header(f"BPTT: 4 agents x 64 steps, k = 8, w_goal = {w_goal}, {N_DIRECTIONS} directions")
+    loss, g_s0, g_a = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal)
+    l_ref = ograd.rollout_loss(s0, acts, p, sc, goals, VIEW64, w_goal=w_goal)
+    assert abs(loss - l_ref) <= 1e-4 * abs(l_ref)
+    worst, jumps = 0.0, []
+    for j in range(N_DIRECTIONS):
         u_s = rng.normal(size=s0.shape)
         u_a = rng.normal(size=acts.shape)
         norm = math.sqrt((u_s ** 2).sum() + (u_a ** 2).sum())
         u_s, u_a = u_s / norm, u_a / norm
-        fd, smooth, fd_c, n_jumps = ograd.rollout_directional(s0, acts, p, sc, goals, view, u_s, u_a, h=1e-6, d0=d0,
-                                                              w_goal=w_goal)
-        ad = float((g_s0 * u_s).sum() + (g_a * u_a).sum())
-        print(f"[gpu-test] direction {j}: adjoint {ad:.6e} fd {fd:.6e} fd off jumps {fd_c:.6e} "
-              f"({n_jumps} jumped pixel-steps of {H * n * 4096})", flush=True)
-        # a handful of silhouette pixels carry no smooth information worth more than 1e-4 relative
-        if n_jumps > 20:
-            continue
-        assert abs(ad - fd_c) <= 2e-3 * max(abs(fd_c), 1e-3), f"direction {j}: adjoint {ad} vs fd {fd_c}"
-        checked += 1
-    assert checked >= 2
+        fd, smooth, fd_c, n_jumps, jumped = ograd.rollout_directional(s0, acts, p, sc, goals, VIEW64, u_s, u_a,
+                                                                      h=1e-6, w_goal=w_goal, return_jumps=True)
+        if n_jumps:
+            _, gs, ga = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal, keep=~jumped)
+        else:
+            gs, ga = g_s0, g_a
+        ad = float((gs * u_s).sum() + (ga * u_a).sum())
+        rel = abs(ad - fd_c) / max(abs(fd_c), 1e-3)
+        print(f"[gpu-test] direction {j}: adjoint {ad:.6e} fd {fd_c:.6e} rel {rel:.2e} "
+              f"({n_jumps} jumped pixel-steps of {H * n * 4096} removed)", flush=True)
+        assert rel <= BPTT_TOL, f"direction {j}: adjoint {ad} vs fd {fd_c} (rel {rel:.2e})"
+        worst = max(worst, rel)
+        jumps.append(n_jumps)
+    record(f"bptt_directions[w_goal={w_goal}]", compared=N_DIRECTIONS, of=N_DIRECTIONS, worst_rel=worst,
+           bound=BPTT_TOL, jumped_pixel_steps=jumps)
+    ctx.free_scene(sid)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("agent", [0, 1, 2, 3])
+def test_bptt_coordinates_vs_oracle_fd(vf, agent):
+    """Per-coordinate gradients of the rollout loss (w_goal = 0.01) for one agent of the differentiable
+    configuration, in a crop of the forest around it: the 4 action components at steps 0, 31 and 63 and
+    the 17 start-state components, each against FP64 central differences (h = 1e-6) of the oracle,
+    within 1e-3 relative.  A coordinate whose derivative is under 1% of the largest of its group (the
+    actions of one step, or the start state) is held to 1e-3 of that 1%: float32 adjoint errors scale
+    with the group's largest terms.  Jumped pixel-steps are removed from both sides as above."""
+    sim, ctx = vf
+    from paper_2407_14783_amd import autograd as vag
+    p, sc, s0, acts, goals, _ = _bptt_setup(agent)
+    H = acts.shape[0]
+    w_goal = 0.01
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    header(f"BPTT coordinates: agent {agent}, {sc['tris'].shape[0]} triangles, 64 steps")
+    loss, g_s0, g_a = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal)
+    # FP64 oracle states s_k (dynamics only) to start the differences at step k from
+    traj = odyn.rollout(s0.astype(np.float64), acts.astype(np.float64), p)
+    groups = [("a0", 0), ("a31", 31), ("a63", 63), ("s0", None)]
+    worst = 0.0
+    n_checked = 0
+    for name, k in groups:
+        start = 0 if k is None else k
+        dim = 17 if k is None else 4
+        fds, ads = [], []
+        for c in range(dim):
+            u_s = np.zeros((1, 17))
+            u_a = np.zeros((H - start, 1, 4))
+            if k is None:
+                u_s[0, c] = 1.0
+            else:
+                u_a[0, 0, c] = 1.0
+            fd, smooth, fd_c, n_jumps, jumped = ograd.rollout_directional(
+                traj[start], acts[start:], p, sc, goals, VIEW64, u_s, u_a, h=1e-6, w_goal=w_goal,
+                return_jumps=True)
+            if n_jumps:
+                keep = np.ones((H, 1, 4096), dtype=bool)
+                keep[start:] = ~jumped
+                _, gs, ga = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal, keep=keep)
+            else:
+                gs, ga = g_s0, g_a
+            fds.append(fd_c)
+            ads.append(gs[0, c] if k is None else ga[k, 0, c])
+        fds, ads = np.asarray(fds), np.asarray(ads)
+        floor = 1e-2 * np.abs(fds).max()
+        rel = np.abs(ads - fds) / np.maximum(np.abs(fds), floor)
+        print(f"[gpu-test] agent {agent} {name}: fd {np.array2string(fds, precision=4)} "
+              f"max rel {rel.max():.2e}", flush=True)
+        assert rel.max() <= BPTT_TOL, f"agent {agent} {name}: component {int(np.argmax(rel))} rel {rel.max():.2e}"
+        worst = max(worst, float(rel.max()))
+        n_checked += dim
+    record(f"bptt_coordinates[agent {agent}]", coordinates=n_checked, worst_rel=worst, bound=BPTT_TOL)
     ctx.free_scene(sid)
 
 

@@ -14,7 +14,7 @@ import torch
 
 from oracle import dynamics as odyn
 from oracle import render as oren
-from workloads import agents, default_params, scenes
+from workloads import agents, default_params, device_params, scenes
 from tests.gpu_util import compare_render, header
 
 pytestmark = pytest.mark.gpu
@@ -116,7 +116,7 @@ def test_swarm_step_and_collision(vf):
     ctx.sync_check()
     ctx.set_launch_mode(None)
     s1 = st.cpu().numpy()
-    ref_s1 = odyn.step(st0, acts, p)
+    ref_s1 = odyn.step(st0, acts, device_params(p))
     assert np.abs(s1 - ref_s1).max() < 1e-5
     depth, ids = depth.cpu().numpy(), ids.cpu().numpy()
     for i in range(n):

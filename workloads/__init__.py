@@ -6,7 +6,7 @@ cast to float32 once.  It contains none of the simulator's arithmetic (no
 dynamics, no ray casting); both the oracle and the device path receive the
 same arrays from here and compute independently.
 """
-from .params import default_params, PARAM_FIELDS
+from .params import default_params, device_params, PARAM_FIELDS
 from . import scenes, agents
 
-__all__ = ["default_params", "PARAM_FIELDS", "scenes", "agents"]
+__all__ = ["default_params", "device_params", "PARAM_FIELDS", "scenes", "agents"]

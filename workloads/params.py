@@ -59,3 +59,19 @@ def default_params(**overrides):
             raise KeyError(f"unknown parameter {k!r}")
         p[k] = v
     return p
+
+
+def device_params(p):
+    """The parameter values the device receives: every real field rounded to float32 once (the C parameter
+    block holds float32), as plain Python floats.  Comparing the FP64 oracle with the device on these
+    values compares the arithmetic, with the same inputs on both sides."""
+    import numpy as np
+    out = {}
+    for k, v in p.items():
+        if isinstance(v, float):
+            out[k] = float(np.float32(v))
+        elif isinstance(v, tuple):
+            out[k] = tuple(float(np.float32(x)) for x in v)
+        else:
+            out[k] = v
+    return out
