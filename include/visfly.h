@@ -324,6 +324,9 @@ vf_status vf_imu(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int3
 
 /* ---------------------------------------------------------------------------
  * Swarm mode (the swarm example of Sec. IV: agents see and avoid each other).
+ * Renders find the members through a top-level tree per swarm, rebuilt from the states before every
+ * vf_step / vf_render that shows swarms (members in Morton order, four to a leaf, an implicit 4-wide
+ * tree of their world-axis boxes; one tree buffer per stream).  At most 4,096 members per swarm.
  * Swarm s has the state slots slots[offsets[s] .. offsets[s + 1]) (host arrays, copied; the slots index
  * the state array of the later calls).  A view with swarm = s + 1 renders the other members of swarm s
  * as boxes of half sizes half_extent centred on their positions and turned with their attitude, in the
@@ -397,7 +400,8 @@ vf_status vf_set_stats(vf_ctx* ctx, int32_t enable);
  * in a packet whose rays share one direction octant, 14 where they differ in the sign of
  * one axis, 18 otherwise), out[7] hits, out[8] node visits, out[9] ray-box tests and
  * out[10] ray-triangle tests a lane's own ray asked for (visits of nodes and leaves whose
- * box that ray entered), out[11] 0.  Synchronises the device. */
+ * box that ray entered), out[11] swarm member tests (oriented member boxes tested per
+ * lane; the member trees' box tests are in out[2]).  Synchronises the device. */
 #define VF_STAT_COUNT 12
 vf_status vf_stats_read(vf_ctx* ctx, uint64_t out[VF_STAT_COUNT], int32_t reset);
 
@@ -466,6 +470,8 @@ typedef struct vf_request_out {
 
 typedef struct vf_server_stats {
     int64_t batches, agents, requests, max_batch_agents, pending, in_flight_batches;
+    int64_t requeued;          /* requests queued again after their batch failed */
+    int64_t failed_batches;    /* batches that failed to launch or were reported failed */
 } vf_server_stats;
 
 /* state_table [n_slots][17] float32 [dev]: resident env states, updated in place. */
@@ -487,6 +493,13 @@ vf_status vf_server_poll(vf_server* s, int64_t ticket, int32_t* done);
 vf_status vf_server_wait(vf_server* s, int64_t ticket, float* depth, int32_t* tri_id, uint8_t* rgb, float* state,
                          double* latency_s);
 vf_status vf_server_stats_get(vf_server* s, vf_server_stats* out);
+/* A host-forced backend error, for failure-path runs: the next n batches that finish are treated as
+ * failed.  Each such batch's env slots are restored to their states before it (the batch saves them
+ * before its step) and its requests go back to the front of the queue, in order; a request that has
+ * been in 8 failed batches fails with VF_EHIP.  Results are unchanged by the retries.  The environment
+ * variable VF_FAULT_INJECT=n at vf_server_create does the same for the server's first n batches.
+ * A batch that fails to launch is handled the same way. */
+vf_status vf_server_inject_faults(vf_server* s, int64_t n);
 /* VF_EBUSY while requests are pending; in-flight batches are drained. */
 vf_status vf_server_destroy(vf_server* s);
 

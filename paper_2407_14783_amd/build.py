@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvisfly_hip.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["runtime.cpp", "bvh_build.hip", "render.hip", "grad.hip", "query.hip", "sensors.hip", "serve.cpp"]
+SOURCES = ["runtime.cpp", "bvh_build.hip", "render.hip", "grad.hip", "query.hip", "sensors.hip", "swarm.hip",
+           "serve.cpp"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

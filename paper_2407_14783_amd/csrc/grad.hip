@@ -1,10 +1,10 @@
 // Adjoint kernels for the differentiable forms (Sec. III-A: differentiable
 // dynamics whose analytic gradients drive learning).
 //
-// k_step_backward: reverse mode of one control step, written out by hand.  The
-// forward sub-steps are recomputed from the saved state (for sub-step j the
-// forward runs j sub-steps from the start, so n_sub sub-steps cost n_sub(n_sub+1)/2
-// forward sub-steps; n_sub is small).  Within a sub-step the RK4 stages are
+// k_step_backward: reverse mode of one control step, written out by hand, in FP64
+// like the forward step.  The forward sub-steps are recomputed from the saved state
+// (for sub-step j the forward runs j sub-steps from the start, so n_sub sub-steps cost
+// n_sub(n_sub+1)/2 forward sub-steps; n_sub is small).  Within a sub-step the RK4 stages are
 // recomputed and walked backwards: normalisation, the RK4 combination, the four
 // stage derivatives (Eq. 1 with Eq. 2 drag and Eq. 3 wrench), the closed-form
 // rotor lag (Eq. 4), the square root, the clamp (zero gradient when clamped)
@@ -14,90 +14,94 @@
 // dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B with d_B = R_m d_cam and
 // o = p + R t_m for a camera mounted at (R_m, t_m).  Per agent the pixel
 // sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix) are reduced in
-// a fixed order, then chained through R and the quaternion normalisation.
+// a fixed order (accumulated in FP64), then chained through R and the quaternion normalisation.
 #include "dynamics.h"
 #include "vf_internal.h"
 
 namespace vf {
 
 // d/dq of sum_ij G_ij R_ij(q) for a unit quaternion q (no normalisation term).
-__device__ __forceinline__ void rot_vjp(const float q[4], const float G[9], float out[4]) {
-    float w = q[0], x = q[1], y = q[2], z = q[3];
-    out[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
-    out[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] - 2.f * x * G[8]);
-    out[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - 2.f * y * G[8]);
-    out[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
+template <typename T>
+__device__ __forceinline__ void rot_vjp(const T q[4], const T G[9], T out[4]) {
+    const T w = q[0], x = q[1], y = q[2], z = q[3];
+    out[0] = T(2) * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    out[1] = T(2) * (y * G[1] + z * G[2] + y * G[3] - T(2) * x * G[4] - w * G[5] + z * G[6] + w * G[7] - T(2) * x * G[8]);
+    out[2] = T(2) * (-T(2) * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - T(2) * y * G[8]);
+    out[3] = T(2) * (-T(2) * z * G[0] - w * G[1] + x * G[2] + w * G[3] - T(2) * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
 }
 
 // lambda_q of q -> q/|q| given lambda on the normalised value.
-__device__ __forceinline__ void normalize_vjp(const float q[4], const float lam_n[4], float lam_q[4]) {
-    float n = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    float inv = 1.0f / n;
-    float qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
-    float dot = qn[0] * lam_n[0] + qn[1] * lam_n[1] + qn[2] * lam_n[2] + qn[3] * lam_n[3];
+template <typename T>
+__device__ __forceinline__ void normalize_vjp(const T q[4], const T lam_n[4], T lam_q[4]) {
+    const T n = vsqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const T inv = T(1) / n;
+    const T qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
+    const T dot = qn[0] * lam_n[0] + qn[1] * lam_n[1] + qn[2] * lam_n[2] + qn[3] * lam_n[3];
     for (int i = 0; i < 4; ++i) lam_q[i] = (lam_n[i] - qn[i] * dot) * inv;
 }
 
 // VJP of c(om) = om x (J om): returns d/d om of lam . c.
-__device__ __forceinline__ void gyro_vjp(const DynConst& c, const float om[3], const float lam[3], float out[3]) {
-    float j[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
+template <typename T>
+__device__ __forceinline__ void gyro_vjp(const DynConstT<T>& c, const T om[3], const T lam[3], T out[3]) {
+    const T j[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
     // j x lam
-    float a0 = j[1] * lam[2] - j[2] * lam[1];
-    float a1 = j[2] * lam[0] - j[0] * lam[2];
-    float a2 = j[0] * lam[1] - j[1] * lam[0];
+    const T a0 = j[1] * lam[2] - j[2] * lam[1];
+    const T a1 = j[2] * lam[0] - j[0] * lam[2];
+    const T a2 = j[0] * lam[1] - j[1] * lam[0];
     // J (lam x om)
-    float b0 = c.J[0] * (lam[1] * om[2] - lam[2] * om[1]);
-    float b1 = c.J[1] * (lam[2] * om[0] - lam[0] * om[2]);
-    float b2 = c.J[2] * (lam[0] * om[1] - lam[1] * om[0]);
+    const T b0 = c.J[0] * (lam[1] * om[2] - lam[2] * om[1]);
+    const T b1 = c.J[1] * (lam[2] * om[0] - lam[0] * om[2]);
+    const T b2 = c.J[2] * (lam[0] * om[1] - lam[1] * om[0]);
     out[0] = a0 + b0;
     out[1] = a1 + b1;
     out[2] = a2 + b2;
 }
 
 // Reverse of derivative(): given the cotangent L of d = F(y, w), accumulate into ly, lw.
-__device__ __forceinline__ void derivative_vjp(const DynConst& c, const Vec13& y, const float w[4], const Vec13& L,
-                                               Vec13& ly, float lw[4]) {
-    float f[4] = {w[0] * w[0], w[1] * w[1], w[2] * w[2], w[3] * w[3]};
-    float fz, tau[3];
+template <typename T>
+__device__ __forceinline__ void derivative_vjp(const DynConstT<T>& c, const Vec13T<T>& y, const T w[4],
+                                               const Vec13T<T>& L, Vec13T<T>& ly, T lw[4]) {
+    const T f[4] = {w[0] * w[0], w[1] * w[1], w[2] * w[2], w[3] * w[3]};
+    T fz, tau[3];
     rotor_wrench(c, f, fz, tau);
-    float r[9];
-    quat_rot(y.q, r);
-    float vb[3];
+    T r[9];
+    body_rot(y.q, r);
+    T vb[3];
     for (int i = 0; i < 3; ++i) vb[i] = r[0 + i] * y.v[0] + r[3 + i] * y.v[1] + r[6 + i] * y.v[2];
-    float fb[3];
-    for (int i = 0; i < 3; ++i) fb[i] = -c.k_lin[i] * vb[i] - c.c_quad[i] * fabsf(vb[i]) * vb[i];
+    T fb[3];
+    for (int i = 0; i < 3; ++i) fb[i] = -c.k_lin[i] * vb[i] - c.c_quad[i] * vabs(vb[i]) * vb[i];
     fb[2] += fz;
     // d.p = v
     for (int i = 0; i < 3; ++i) ly.v[i] += L.p[i];
     // d.v = R fb / m - g z
-    float lv[3] = {L.v[0] * c.inv_mass, L.v[1] * c.inv_mass, L.v[2] * c.inv_mass};
-    float G[9];
+    const T lv[3] = {L.v[0] * c.inv_mass, L.v[1] * c.inv_mass, L.v[2] * c.inv_mass};
+    T G[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) G[3 * i + j] = lv[i] * fb[j];
-    float lfb[3];
+    T lfb[3];
     for (int j = 0; j < 3; ++j) lfb[j] = r[j] * lv[0] + r[3 + j] * lv[1] + r[6 + j] * lv[2];
-    float lfz = lfb[2];
-    float lvb[3];
-    for (int i = 0; i < 3; ++i) lvb[i] = lfb[i] * (-c.k_lin[i] - 2.0f * c.c_quad[i] * fabsf(vb[i]));
+    const T lfz = lfb[2];
+    T lvb[3];
+    for (int i = 0; i < 3; ++i) lvb[i] = lfb[i] * (-c.k_lin[i] - T(2) * c.c_quad[i] * vabs(vb[i]));
     // vb_i = sum_j R_ji v_j
     for (int j = 0; j < 3; ++j) ly.v[j] += r[3 * j + 0] * lvb[0] + r[3 * j + 1] * lvb[1] + r[3 * j + 2] * lvb[2];
     for (int j = 0; j < 3; ++j)
         for (int i = 0; i < 3; ++i) G[3 * j + i] += y.v[j] * lvb[i];
     // R = R(q/|q|)
     {
-        float n = sqrtf(y.q[0] * y.q[0] + y.q[1] * y.q[1] + y.q[2] * y.q[2] + y.q[3] * y.q[3]);
-        float inv = 1.0f / n;
-        float qn[4] = {y.q[0] * inv, y.q[1] * inv, y.q[2] * inv, y.q[3] * inv};
-        float lqn[4], lq[4];
+        const T n = vsqrt(y.q[0] * y.q[0] + y.q[1] * y.q[1] + y.q[2] * y.q[2] + y.q[3] * y.q[3]);
+        const T inv = T(1) / n;
+        const T qn[4] = {y.q[0] * inv, y.q[1] * inv, y.q[2] * inv, y.q[3] * inv};
+        T lqn[4], lq[4];
         rot_vjp(qn, G, lqn);
         normalize_vjp(y.q, lqn, lq);
         for (int i = 0; i < 4; ++i) ly.q[i] += lq[i];
     }
     // d.q = 1/2 q (x) (0, om)
     {
-        const float* q = y.q;
-        const float* om = y.w;
-        float a = 0.5f * L.q[0], b = 0.5f * L.q[1], cc = 0.5f * L.q[2], d = 0.5f * L.q[3];
+        const T* q = y.q;
+        const T* om = y.w;
+        const T a = T(0.5) * L.q[0], b = T(0.5) * L.q[1], cc = T(0.5) * L.q[2], d = T(0.5) * L.q[3];
         ly.q[0] += b * om[0] + cc * om[1] + d * om[2];
         ly.q[1] += -a * om[0] - cc * om[2] + d * om[1];
         ly.q[2] += -a * om[1] + b * om[2] - d * om[0];
@@ -107,101 +111,104 @@ __device__ __forceinline__ void derivative_vjp(const DynConst& c, const Vec13& y
         ly.w[2] += -a * q[3] + b * q[2] - cc * q[1] + d * q[0];
     }
     // d.w = J^-1 (tau - om x J om)
-    float ltau[3] = {L.w[0] * c.inv_J[0], L.w[1] * c.inv_J[1], L.w[2] * c.inv_J[2]};
+    const T ltau[3] = {L.w[0] * c.inv_J[0], L.w[1] * c.inv_J[1], L.w[2] * c.inv_J[2]};
     {
-        float lc[3] = {-ltau[0], -ltau[1], -ltau[2]};
-        float g[3];
+        const T lc[3] = {-ltau[0], -ltau[1], -ltau[2]};
+        T g[3];
         gyro_vjp(c, y.w, lc, g);
         for (int i = 0; i < 3; ++i) ly.w[i] += g[i];
     }
     // tau, fz from f
-    float a = c.arm_a, k = c.kappa;
-    float lf[4];
+    const T a = c.arm_a, k = c.kappa;
+    T lf[4];
     lf[0] = lfz - a * ltau[0] - a * ltau[1] + k * ltau[2];
     lf[1] = lfz + a * ltau[0] + a * ltau[1] + k * ltau[2];
     lf[2] = lfz + a * ltau[0] - a * ltau[1] - k * ltau[2];
     lf[3] = lfz - a * ltau[0] + a * ltau[1] - k * ltau[2];
-    for (int i = 0; i < 4; ++i) lw[i] += 2.0f * w[i] * lf[i];
+    for (int i = 0; i < 4; ++i) lw[i] += T(2) * w[i] * lf[i];
 }
 
-__device__ __forceinline__ void zero13(Vec13& v) {
-    for (int i = 0; i < 3; ++i) { v.p[i] = 0.f; v.v[i] = 0.f; v.w[i] = 0.f; }
-    for (int i = 0; i < 4; ++i) v.q[i] = 0.f;
+template <typename T>
+__device__ __forceinline__ void zero13(Vec13T<T>& v) {
+    for (int i = 0; i < 3; ++i) { v.p[i] = T(0); v.v[i] = T(0); v.w[i] = T(0); }
+    for (int i = 0; i < 4; ++i) v.q[i] = T(0);
 }
 
-__device__ __forceinline__ void load13(Vec13& y, const float s[17]) {
+template <typename T>
+__device__ __forceinline__ void load13(Vec13T<T>& y, const T s[17]) {
     for (int i = 0; i < 3; ++i) { y.p[i] = s[i]; y.v[i] = s[7 + i]; y.w[i] = s[10 + i]; }
     for (int i = 0; i < 4; ++i) y.q[i] = s[3 + i];
 }
 
-// Reverse of one sub-step starting at state s with action act; lam (17) is the
-// cotangent of the sub-step output and is overwritten with the cotangent of s;
-// la (4) accumulates the action cotangent.
-__device__ void substep_vjp(const DynConst& c, const float s[17], const float act[4], float lam[17], float la[4]) {
+// Reverse of one CTBR / SRT sub-step (dyn_substep) starting at state s with action act, in FP64; lam (17)
+// is the cotangent of the sub-step output and is overwritten with the cotangent of s; la (4) accumulates
+// the action cotangent.
+__device__ void substep_vjp(const DynConstD& c, const double s[17], const double act[4], double lam[17],
+                            double la[4]) {
+#pragma clang fp contract(off)
     // ---- recompute the forward sub-step ----
-    float fraw[4], fdes[4], wd[4], w0[4], wh[4], wf[4];
+    double fraw[4], fdes[4], wd[4], w0[4], wh[4], wf[4];
     if (c.ctrl == VF_SRT) {
         for (int i = 0; i < 4; ++i) fraw[i] = act[i];
     } else {
-        const float* om = s + 10;
-        float jo[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
-        float t0 = c.kJ[0] * (act[1] - om[0]) + (om[1] * jo[2] - om[2] * jo[1]);
-        float t1 = c.kJ[1] * (act[2] - om[1]) + (om[2] * jo[0] - om[0] * jo[2]);
-        float t2 = c.kJ[2] * (act[3] - om[2]) + (om[0] * jo[1] - om[1] * jo[0]);
-        float u0 = c.mass * act[0], u1 = t0 * c.inv_a, u2 = t1 * c.inv_a, u3 = t2 * c.inv_kappa;
-        fraw[0] = 0.25f * ((u0 + u3) - (u1 + u2));
-        fraw[1] = 0.25f * ((u0 + u3) + (u1 + u2));
-        fraw[2] = 0.25f * ((u0 - u3) + (u1 - u2));
-        fraw[3] = 0.25f * ((u0 - u3) - (u1 - u2));
+        const double* om = s + 10;
+        const double jo[3] = {c.J[0] * om[0], c.J[1] * om[1], c.J[2] * om[2]};
+        const double t0 = c.kJ[0] * (act[1] - om[0]) + (om[1] * jo[2] - om[2] * jo[1]);
+        const double t1 = c.kJ[1] * (act[2] - om[1]) + (om[2] * jo[0] - om[0] * jo[2]);
+        const double t2 = c.kJ[2] * (act[3] - om[2]) + (om[0] * jo[1] - om[1] * jo[0]);
+        const double u0 = c.mass * act[0], u1 = t0 * c.inv_a, u2 = t1 * c.inv_a, u3 = t2 * c.inv_kappa;
+        fraw[0] = 0.25 * ((u0 + u3) - (u1 + u2));
+        fraw[1] = 0.25 * ((u0 + u3) + (u1 + u2));
+        fraw[2] = 0.25 * ((u0 - u3) + (u1 - u2));
+        fraw[3] = 0.25 * ((u0 - u3) - (u1 - u2));
     }
     for (int i = 0; i < 4; ++i) {
-        fdes[i] = fminf(fmaxf(fraw[i], 0.0f), c.f_max);
-        wd[i] = sqrtf(fdes[i]);
+        fdes[i] = fmin(fmax(fraw[i], 0.0), c.f_max);
+        wd[i] = sqrt(fdes[i]);
         w0[i] = s[13 + i];
         wh[i] = wd[i] + (w0[i] - wd[i]) * c.e_half;
         wf[i] = wd[i] + (w0[i] - wd[i]) * c.e_full;
     }
-    const float h = c.h;
-    Vec13 y, y1, y2, y3, k1, k2, k3, k4, yn;
+    const double h = c.h;
+    Vec13T<double> y, y1, y2, y3, k1, k2, k3, k4, yn;
     load13(y, s);
     derivative(c, y, w0, k1);
-    bool euler = c.integrator == VF_EULER;
+    const bool euler = c.integrator == VF_EULER;
     if (euler) {
         axpy13(yn, y, h, k1);
     } else {
-        axpy13(y1, y, 0.5f * h, k1);
+        axpy13(y1, y, 0.5 * h, k1);
         derivative(c, y1, wh, k2);
-        axpy13(y2, y, 0.5f * h, k2);
+        axpy13(y2, y, 0.5 * h, k2);
         derivative(c, y2, wh, k3);
         axpy13(y3, y, h, k3);
         derivative(c, y3, wf, k4);
-        const float h6 = h * (1.0f / 6.0f);
+        const double h6 = h / 6.0;
         for (int i = 0; i < 3; ++i) {
-            yn.p[i] = y.p[i] + h6 * (k1.p[i] + 2.0f * (k2.p[i] + k3.p[i]) + k4.p[i]);
-            yn.v[i] = y.v[i] + h6 * (k1.v[i] + 2.0f * (k2.v[i] + k3.v[i]) + k4.v[i]);
-            yn.w[i] = y.w[i] + h6 * (k1.w[i] + 2.0f * (k2.w[i] + k3.w[i]) + k4.w[i]);
+            yn.p[i] = y.p[i] + h6 * (k1.p[i] + 2.0 * (k2.p[i] + k3.p[i]) + k4.p[i]);
+            yn.v[i] = y.v[i] + h6 * (k1.v[i] + 2.0 * (k2.v[i] + k3.v[i]) + k4.v[i]);
+            yn.w[i] = y.w[i] + h6 * (k1.w[i] + 2.0 * (k2.w[i] + k3.w[i]) + k4.w[i]);
         }
-        for (int i = 0; i < 4; ++i) yn.q[i] = y.q[i] + h6 * (k1.q[i] + 2.0f * (k2.q[i] + k3.q[i]) + k4.q[i]);
+        for (int i = 0; i < 4; ++i) yn.q[i] = y.q[i] + h6 * (k1.q[i] + 2.0 * (k2.q[i] + k3.q[i]) + k4.q[i]);
     }
     // ---- reverse ----
-    float lwf[4], lwh[4] = {0.f, 0.f, 0.f, 0.f}, lw0[4] = {0.f, 0.f, 0.f, 0.f};
+    double lwf[4], lwh[4] = {0.0, 0.0, 0.0, 0.0}, lw0[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < 4; ++i) lwf[i] = lam[13 + i];
-    Vec13 lyn;
+    Vec13T<double> lyn;
     for (int i = 0; i < 3; ++i) { lyn.p[i] = lam[i]; lyn.v[i] = lam[7 + i]; lyn.w[i] = lam[10 + i]; }
     {
-        float lqn[4] = {lam[3], lam[4], lam[5], lam[6]};
+        const double lqn[4] = {lam[3], lam[4], lam[5], lam[6]};
         normalize_vjp(yn.q, lqn, lyn.q);
     }
-    Vec13 ly = lyn;
+    Vec13T<double> ly = lyn;
     if (euler) {
-        Vec13 lk1, tmp;
-        zero13(tmp);
+        Vec13T<double> lk1;
         for (int i = 0; i < 3; ++i) { lk1.p[i] = h * lyn.p[i]; lk1.v[i] = h * lyn.v[i]; lk1.w[i] = h * lyn.w[i]; }
         for (int i = 0; i < 4; ++i) lk1.q[i] = h * lyn.q[i];
         derivative_vjp(c, y, w0, lk1, ly, lw0);
     } else {
-        const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
-        Vec13 lk1, lk2, lk3, lk4, l3, l2, l1;
+        const double h6 = h / 6.0, h3 = h / 3.0;
+        Vec13T<double> lk1, lk2, lk3, lk4, l3, l2, l1;
         for (int i = 0; i < 3; ++i) {
             lk1.p[i] = h6 * lyn.p[i]; lk2.p[i] = h3 * lyn.p[i]; lk3.p[i] = h3 * lyn.p[i]; lk4.p[i] = h6 * lyn.p[i];
             lk1.v[i] = h6 * lyn.v[i]; lk2.v[i] = h3 * lyn.v[i]; lk3.v[i] = h3 * lyn.v[i]; lk4.v[i] = h6 * lyn.v[i];
@@ -213,45 +220,45 @@ __device__ void substep_vjp(const DynConst& c, const float s[17], const float ac
         // k4 = F(y3, wf), y3 = y + h k3
         zero13(l3);
         derivative_vjp(c, y3, wf, lk4, l3, lwf);
-        axpy13(ly, ly, 1.0f, l3);
+        axpy13(ly, ly, 1.0, l3);
         axpy13(lk3, lk3, h, l3);
         // k3 = F(y2, wh), y2 = y + h/2 k2
         zero13(l2);
         derivative_vjp(c, y2, wh, lk3, l2, lwh);
-        axpy13(ly, ly, 1.0f, l2);
-        axpy13(lk2, lk2, 0.5f * h, l2);
+        axpy13(ly, ly, 1.0, l2);
+        axpy13(lk2, lk2, 0.5 * h, l2);
         // k2 = F(y1, wh), y1 = y + h/2 k1
         zero13(l1);
         derivative_vjp(c, y1, wh, lk2, l1, lwh);
-        axpy13(ly, ly, 1.0f, l1);
-        axpy13(lk1, lk1, 0.5f * h, l1);
+        axpy13(ly, ly, 1.0, l1);
+        axpy13(lk1, lk1, 0.5 * h, l1);
         // k1 = F(y, w0)
         derivative_vjp(c, y, w0, lk1, ly, lw0);
     }
     // rotor lag: wh = wd + (w0 - wd) e_half, wf = wd + (w0 - wd) e_full
-    float lwd[4], lf[4];
+    double lwd[4], lf[4];
     for (int i = 0; i < 4; ++i) {
         lw0[i] += c.e_half * lwh[i] + c.e_full * lwf[i];
-        lwd[i] = (1.0f - c.e_half) * lwh[i] + (1.0f - c.e_full) * lwf[i];
+        lwd[i] = (1.0 - c.e_half) * lwh[i] + (1.0 - c.e_full) * lwf[i];
         // wd = sqrt(fdes), fdes = clamp(fraw)
-        bool inside = fraw[i] > 0.0f && fraw[i] < c.f_max;
-        lf[i] = (inside && wd[i] > 0.0f) ? lwd[i] * 0.5f / wd[i] : 0.0f;
+        const bool inside = fraw[i] > 0.0 && fraw[i] < c.f_max;
+        lf[i] = (inside && wd[i] > 0.0) ? lwd[i] * 0.5 / wd[i] : 0.0;
     }
-    float lom_ctrl[3] = {0.f, 0.f, 0.f};
+    double lom_ctrl[3] = {0.0, 0.0, 0.0};
     if (c.ctrl == VF_SRT) {
         for (int i = 0; i < 4; ++i) la[i] += lf[i];
     } else {
-        float lu0 = 0.25f * ((lf[0] + lf[1]) + (lf[2] + lf[3]));
-        float lu1 = 0.25f * ((lf[1] + lf[2]) - (lf[0] + lf[3]));
-        float lu2 = 0.25f * ((lf[1] + lf[3]) - (lf[0] + lf[2]));
-        float lu3 = 0.25f * ((lf[0] + lf[1]) - (lf[2] + lf[3]));
-        float lt[3] = {lu1 * c.inv_a, lu2 * c.inv_a, lu3 * c.inv_kappa};
+        const double lu0 = 0.25 * ((lf[0] + lf[1]) + (lf[2] + lf[3]));
+        const double lu1 = 0.25 * ((lf[1] + lf[2]) - (lf[0] + lf[3]));
+        const double lu2 = 0.25 * ((lf[1] + lf[3]) - (lf[0] + lf[2]));
+        const double lu3 = 0.25 * ((lf[0] + lf[1]) - (lf[2] + lf[3]));
+        const double lt[3] = {lu1 * c.inv_a, lu2 * c.inv_a, lu3 * c.inv_kappa};
         la[0] += c.mass * lu0;
         for (int k = 0; k < 3; ++k) {
             la[1 + k] += c.kJ[k] * lt[k];
             lom_ctrl[k] -= c.kJ[k] * lt[k];
         }
-        float g[3];
+        double g[3];
         gyro_vjp(c, s + 10, lt, g);
         for (int k = 0; k < 3; ++k) lom_ctrl[k] += g[k];
     }
@@ -266,36 +273,32 @@ __device__ void substep_vjp(const DynConst& c, const float s[17], const float ac
     }
 }
 
-// One forward sub-step in place (the step's own FP64 sub-step, its state rounded to float32).
-__device__ __forceinline__ void substep_fwd(const DynConstD& c, float s[17], const float a[4]) {
-    DynConstD one = c;
-    one.n_sub = 1;
-    dyn_step(one, s, a, s);
-}
-
+// One thread per agent: the control step's sub-step states are recomputed from the saved state in FP64
+// exactly as dyn_step computed them, then walked in reverse; the cotangents are carried in FP64 and
+// rounded to float32 once at the end.
 __global__ void __launch_bounds__(128) k_step_backward(StepBackArgs a) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    float s0[17], act[4], lam[17], la[4] = {0.f, 0.f, 0.f, 0.f};
+    double s0[17], act[4], lam[17], la[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < 17; ++k) {
-        s0[k] = a.state_in[(int64_t)i * 17 + k];
-        lam[k] = a.grad_out[(int64_t)i * 17 + k];
+        s0[k] = (double)a.state_in[(int64_t)i * 17 + k];
+        lam[k] = (double)a.grad_out[(int64_t)i * 17 + k];
     }
-    for (int k = 0; k < 4; ++k) act[k] = a.action[(int64_t)i * 4 + k];
+    for (int k = 0; k < 4; ++k) act[k] = (double)a.action[(int64_t)i * 4 + k];
     for (int sub = a.dyn.n_sub - 1; sub >= 0; --sub) {
-        float s[17];
+        double s[17];
         for (int k = 0; k < 17; ++k) s[k] = s0[k];
-        for (int j = 0; j < sub; ++j) substep_fwd(a.dynd, s, act);
+        for (int j = 0; j < sub; ++j) dyn_substep(a.dyn, s, act);
         substep_vjp(a.dyn, s, act, lam, la);
     }
-    for (int k = 0; k < 17; ++k) a.grad_in[(int64_t)i * 17 + k] = lam[k];
-    for (int k = 0; k < 4; ++k) a.grad_action[(int64_t)i * 4 + k] = la[k];
+    for (int k = 0; k < 17; ++k) a.grad_in[(int64_t)i * 17 + k] = (float)lam[k];
+    for (int k = 0; k < 4; ++k) a.grad_action[(int64_t)i * 4 + k] = (float)la[k];
 }
 
 constexpr int kBackThreads = 256;
 
 __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs a) {
-    __shared__ float red[12][kBackThreads];
+    __shared__ double red[12][kBackThreads];
     const int agent = blockIdx.x;
     vf_view vw = a.views[agent];
     bool ok = vw.scene_id >= 0 && vw.scene_id < a.n_scenes && vw.H >= 1 && vw.W >= 1 && vw.H <= a.max_h &&
@@ -318,8 +321,8 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     float o[3];
     for (int i = 0; i < 3; ++i) o[i] = st[i] + (rot[3 * i] * tm[0] + rot[3 * i + 1] * tm[1] + rot[3 * i + 2] * tm[2]);
     const float tan_h = tanf(0.5f * vw.hfov);
-    float acc[12];
-    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
+    double acc[12];
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     uint32_t bad = 0;
     const int npix = vw.H * vw.W;
     for (int pix = threadIdx.x; pix < npix; pix += kBackThreads) {
@@ -343,10 +346,10 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
         float nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
         if (nd == 0.0f) continue;
         float t = (n[0] * (tr.v0x - o[0]) + n[1] * (tr.v0y - o[1]) + n[2] * (tr.v0z - o[2])) / nd;
-        float s_o = -g / nd, s_d = -g * t / nd;
-        for (int k = 0; k < 3; ++k) acc[k] += s_o * n[k];
+        const double s_o = -(double)g / (double)nd, s_d = -(double)g * (double)t / (double)nd;
+        for (int k = 0; k < 3; ++k) acc[k] += s_o * (double)n[k];
         for (int i2 = 0; i2 < 3; ++i2)
-            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * n[i2] * db[j];
+            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * (double)n[i2] * (double)db[j];
     }
     if (bad) atomicOr(a.err, bad);
     for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = acc[k];
@@ -358,18 +361,19 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     }
     if (threadIdx.x == 0) {
         float* gs = a.grad_state + (int64_t)agent * 17;
-        for (int k = 0; k < 3; ++k) gs[k] += red[k][0];
-        float G[9];
+        for (int k = 0; k < 3; ++k) gs[k] += (float)red[k][0];
+        double G[9];
         for (int k = 0; k < 9; ++k) G[k] = red[3 + k][0];
         // the origin p + R t_m also moves with R
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * tm[j];
-        float inv = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        float qn[4] = {q[0] * inv, q[1] * inv, q[2] * inv, q[3] * inv};
-        float lqn[4], lq[4];
+            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * (double)tm[j];
+        const double qd[4] = {q[0], q[1], q[2], q[3]};
+        const double inv = 1.0 / sqrt(qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
+        const double qn[4] = {qd[0] * inv, qd[1] * inv, qd[2] * inv, qd[3] * inv};
+        double lqn[4], lq[4];
         rot_vjp(qn, G, lqn);
-        normalize_vjp(q, lqn, lq);
-        for (int k = 0; k < 4; ++k) gs[3 + k] += lq[k];
+        normalize_vjp(qd, lqn, lq);
+        for (int k = 0; k < 4; ++k) gs[3 + k] += (float)lq[k];
     }
 }
 

@@ -28,6 +28,7 @@
 // agent's counter writes the new state, so the state can be updated in place.
 #include "dynamics.h"
 #include "noise.h"
+#include "swarm.h"
 #include "vf_internal.h"
 
 namespace vf {
@@ -66,7 +67,7 @@ __device__ __forceinline__ float safe_inv(float x) {
 // in the packet's order would do (with several rays per lane, a lane counts when any of them entered).
 struct TraceStats {
     unsigned long long node_lane, box_lane, tri_lane, node_wave, tri_wave, hits, box_ops, need_node, need_box,
-        need_tri;
+        need_tri, member_lane;
 };
 
 // VALU operations of one ray-box test by the axes whose direction sign is fixed for the packet
@@ -331,51 +332,6 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
         for (int r = 0; r < NR; ++r) ts.hits += (valid[r] && id_best[r] >= 0) ? 1 : 0;
 }
 
-// Swarm members of the view's swarm (other than the agent itself) as boxes turned with their attitude:
-// slab test in each member's body frame, entry depth in [near, far]; a member at the same depth as the
-// mesh hit leaves the mesh hit, and earlier members win ties (their ids are lower).
-template <int NR>
-__device__ __forceinline__ void trace_members(const RenderArgs& a, const vf_view& vw, int64_t self, int32_t n_tris,
-                                              const bool (&valid)[NR], const float o[3], const float (&d)[NR][3],
-                                              float (&t_best)[NR], int32_t (&id_best)[NR]) {
-    if (vw.swarm < 0 || vw.swarm > a.swarm.n) {
-        if (lane_id() == 0) atomicOr(a.err, kErrView);
-        return;
-    }
-    const int b = a.swarm.off[vw.swarm - 1], e = a.swarm.off[vw.swarm];
-    for (int j = b; j < e; ++j) {
-        const int64_t ms = a.swarm.slots[j];
-        if (ms == self) continue;
-        if (ms < 0 || ms >= a.n_slots) {
-            if (lane_id() == 0) atomicOr(a.err, kErrSlot);
-            continue;
-        }
-        const float* mp = a.state + ms * 17;
-        float r[9];
-        quat_rot(mp + 3, r);
-        // o' = R^T (o - c)
-        const float dx = o[0] - mp[0], dy = o[1] - mp[1], dz = o[2] - mp[2];
-        float ob[3];
-        for (int k = 0; k < 3; ++k) ob[k] = r[k] * dx + r[3 + k] * dy + r[6 + k] * dz;
-        const int32_t id = n_tris + (j - b);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            float t_in = -INFINITY, t_out = INFINITY;
-            for (int ax = 0; ax < 3; ++ax) {
-                const float db = r[ax] * d[k][0] + r[3 + ax] * d[k][1] + r[6 + ax] * d[k][2];
-                const float inv = safe_inv(db);
-                const float t1 = (-a.swarm.half[ax] - ob[ax]) * inv, t2 = (a.swarm.half[ax] - ob[ax]) * inv;
-                t_in = fmaxf(t_in, fminf(t1, t2));
-                t_out = fminf(t_out, fmaxf(t1, t2));
-            }
-            const bool take = valid[k] && t_in <= t_out && t_in >= vw.near_clip &&
-                              (t_in < t_best[k] || (t_in == t_best[k] && id_best[k] < 0));
-            t_best[k] = take ? t_in : t_best[k];
-            id_best[k] = take ? id : id_best[k];
-        }
-    }
-}
-
 // Validate an agent's view; returns false (and flags the error) if it cannot be rendered.
 __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) {
     uint32_t bits = 0;
@@ -392,7 +348,7 @@ __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) 
     return true;
 }
 
-template <bool FUSED, bool STATS, bool NOISE>
+template <bool FUSED, bool STATS, bool NOISE, bool SWARM>
 __device__ __forceinline__ void render_body(const RenderArgs& a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
@@ -461,7 +417,7 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     for (int k = 0; k < NR; ++k) pixel_ray(rot, tan_h, vw.H, vw.W, row[k], col[k], d[k]);
     float t_best[NR];
     int32_t id_best[NR];
-    TraceStats ts = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    TraceStats ts = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     int32_t work = 0;
     // one octant for every ray of the packet (lanes outside the image do not count: their best depth
     // of -1 fails every test)?  Then the traversal with the slab planes fixed at compile time.
@@ -509,7 +465,16 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
         default: VF_TRACE(0, 0); break;
     }
 #undef VF_TRACE
-    if (vw.swarm != 0) trace_members<NR>(a, vw, slot, sc.n_tris, valid, o, d, t_best, id_best);
+    if (vw.swarm != 0) {
+        // the other members of the view's swarm, through the swarm's tree (rebuilt for this launch); the
+        // kernels without swarms leave the tree walk out
+        if (!SWARM || vw.swarm < 0 || vw.swarm > a.swarm.n || !a.swarm.nodes) {
+            if (lane == 0) atomicOr(a.err, kErrView);
+        } else if constexpr (SWARM) {
+            trace_swarm<NR, STATS>(a.swarm, vw.swarm - 1, slot, sc.n_tris, valid, o, d, vw.near_clip, t_best,
+                                   id_best, ts.box_lane, ts.member_lane);
+        }
+    }
     // depth goes to the view's own target when the caller gave a table of them, else at out_offset
     float* const dbase = a.depth_views ? a.depth_views[agent] : (a.depth ? a.depth + vw.out_offset : nullptr);
 #pragma unroll
@@ -549,12 +514,12 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
         a.cost[(int64_t)g * kWavesPerBlock + wave] = work;
     if (STATS) {
         // wave reduction of the per-lane counters, one atomic per counter per wave
-        unsigned long long v[10] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
-                                    ts.box_ops, ts.need_node, ts.need_box, ts.need_tri};
+        unsigned long long v[11] = {ts.node_lane, ts.box_lane, ts.tri_lane, ts.node_wave, ts.tri_wave, ts.hits,
+                                    ts.box_ops, ts.need_node, ts.need_box, ts.need_tri, ts.member_lane};
         unsigned long long rays = 0;
         for (int k = 0; k < NR; ++k) rays += valid[k] ? 1 : 0;
         for (int off = 32; off > 0; off >>= 1) {
-            for (int i = 0; i < 10; ++i) v[i] += __shfl_xor(v[i], off);
+            for (int i = 0; i < 11; ++i) v[i] += __shfl_xor(v[i], off);
             rays += __shfl_xor(rays, off);
         }
         if (lane == 0) {
@@ -569,15 +534,17 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
             atomicAdd(&a.stats[8], v[7]);
             atomicAdd(&a.stats[9], v[8]);
             atomicAdd(&a.stats[10], v[9]);
+            atomicAdd(&a.stats[11], v[10]);
         }
     }
 }
 
 // The render kernel of split launches: occupancy of kRenderWavesPerEu waves per SIMD for the traversal.
-template <bool STATS, bool NOISE>
+// SWARM: the views may show swarm members (the tree walk is compiled in).
+template <bool STATS, bool NOISE, bool SWARM>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
 k_render(RenderArgs a) {
-    render_body<false, STATS, NOISE>(a);
+    render_body<false, STATS, NOISE, SWARM>(a);
 }
 
 // The fused kernel (small batches: few workgroups, so occupancy matters less than keeping the one-lane
@@ -585,7 +552,7 @@ k_render(RenderArgs a) {
 template <bool STATS, bool NOISE>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEu)))
 k_render_fused(RenderArgs a) {
-    render_body<true, STATS, NOISE>(a);
+    render_body<true, STATS, NOISE, false>(a);   // swarms always take split launches
 }
 
 __global__ void __launch_bounds__(256) k_step(StepArgs a) {
@@ -612,9 +579,23 @@ __global__ void k_gather_rows(const float* __restrict__ state, const int32_t* __
     out[i] = state[(int64_t)idx[a] * 17 + k];
 }
 
+// Copy rows[i] -> state row idx[i] (one thread per value): puts saved states back.
+__global__ void k_scatter_rows(float* __restrict__ state, const int32_t* __restrict__ idx, int32_t n,
+                               const float* __restrict__ rows) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * 17) return;
+    int a = i / 17, k = i - a * 17;
+    state[(int64_t)idx[a] * 17 + k] = rows[i];
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_scatter_rows(float* state, const int32_t* idx, int32_t n, const float* rows, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_rows, dim3((n * 17 + 255) / 256), dim3(256), 0, st, state, idx, n, rows);
+    return hipGetLastError();
+}
 hipError_t launch_step(const StepArgs& a, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_step, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
@@ -777,16 +758,22 @@ int32_t render_groups_per_agent(int32_t max_h, int32_t max_w) {
 
 template <bool FUSED, bool STATS>
 static void launch_render_noise(bool noise, dim3 grid, dim3 block, hipStream_t st, const RenderArgs& a) {
+    const bool swarm = a.swarm.n > 0 && a.swarm.nodes;
     if (FUSED) {
         if (noise)
             hipLaunchKernelGGL((k_render_fused<STATS, true>), grid, block, 0, st, a);
         else
             hipLaunchKernelGGL((k_render_fused<STATS, false>), grid, block, 0, st, a);
+    } else if (swarm) {
+        if (noise)
+            hipLaunchKernelGGL((k_render<STATS, true, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_render<STATS, false, true>), grid, block, 0, st, a);
     } else {
         if (noise)
-            hipLaunchKernelGGL((k_render<STATS, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_render<STATS, true, false>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((k_render<STATS, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_render<STATS, false, false>), grid, block, 0, st, a);
     }
 }
 

@@ -223,6 +223,7 @@ vf_status vf_destroy(vf_ctx* ctx) {
     ctx_free(ctx, ctx->d_scenes, sizeof(SceneDesc) * kMaxScenes);
     ctx_free(ctx, (void*)ctx->d_labels, sizeof(void*) * kMaxScenes);
     if (ctx->swarm_bytes) ctx_free(ctx, (void*)ctx->swarm.off, ctx->swarm_bytes);
+    for (auto& tr : ctx->swarm_trees) ctx_free(ctx, tr.block, tr.bytes);
     for (auto& o : ctx->orders) ctx_free(ctx, o.order, kStreamScratchBytes);
     for (auto* list : {&ctx->timing_events, &ctx->timing_free})
         for (auto& ev : *list) {
@@ -408,6 +409,34 @@ static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
     a.cost = sc->cost;
 }
 
+// While swarms are set: the member trees of this stream (allocated once per vf_set_swarms generation),
+// rebuilt from the states the render reads, on the render's stream before it.
+static vf_status prepare_swarm(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
+    if (ctx->swarm.n <= 0) return VF_OK;
+    SwarmTree* tree = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto& tr : ctx->swarm_trees)
+            if (tr.stream == (void*)st && tr.gen == ctx->swarm_gen) tree = &tr;
+    }
+    const int64_t node_bytes = ((int64_t)ctx->swarm_nodes * (int64_t)sizeof(Node4) + 255) / 256 * 256;
+    if (!tree) {
+        SwarmTree tr;
+        tr.stream = (void*)st;
+        tr.gen = ctx->swarm_gen;
+        tr.bytes = node_bytes + std::max<int64_t>(ctx->swarm_members, 1) * (int64_t)sizeof(SwarmMember);
+        vf_status s = ctx_alloc(ctx, &tr.block, tr.bytes);
+        if (s != VF_OK) return s;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->swarm_trees.push_back(tr);
+        tree = &ctx->swarm_trees.back();
+    }
+    a.swarm.nodes = (Node4*)tree->block;
+    a.swarm.members = (SwarmMember*)((char*)tree->block + node_bytes);
+    VF_HIP(launch_swarm_tree(a.swarm, a.state, a.n_slots, ctx->d_err, st));
+    return VF_OK;
+}
+
 static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_idx, float* state, int64_t n_slots,
                                    const vf_view* views, int32_t max_h, int32_t max_w, float* depth, int32_t* tri_id,
                                    uint8_t* rgb, int64_t out_pixels) {
@@ -465,6 +494,8 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     if (split) {
         StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
         VF_HIP(launch_step(sa, st));
+        s = prepare_swarm(ctx, a, st);
+        if (s != VF_OK) return s;
         maybe_order(ctx, a, st);
         VF_HIP(timed_render(ctx, a, false, st));
         return VF_OK;
@@ -489,6 +520,8 @@ vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float*
     VF_HIP(hipSetDevice(ctx->device));
     RenderArgs a = make_render_args(ctx, n, env_idx, (float*)state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
                                     out_pixels);
+    s = prepare_swarm(ctx, a, (hipStream_t)stream);
+    if (s != VF_OK) return s;
     maybe_order(ctx, a, (hipStream_t)stream);
     VF_HIP(timed_render(ctx, a, false, (hipStream_t)stream));
     return VF_OK;
@@ -507,7 +540,7 @@ vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, 
         return fail(VF_EINVAL, "vf_step_backward: the adjoint covers the CTBR and SRT controllers");
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
-    StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action, make_dyn_const(*params),
+    StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action,
                    make_dyn_const_d(*params)};
     VF_HIP(launch_step_backward(a, (hipStream_t)stream));
     return VF_OK;
@@ -663,6 +696,9 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
         if (total > 0 && !slots) return fail(VF_EINVAL, "vf_set_swarms: slots is NULL");
         for (int64_t j = 0; j < total; ++j)
             if (slots[j] < 0) return fail(VF_EINVAL, "vf_set_swarms: negative slot");
+        for (int32_t s = 0; s < n_swarms; ++s)
+            if (offsets[s + 1] - offsets[s] > kSwarmMaxMembers)
+                return fail(VF_EINVAL, "vf_set_swarms: a swarm holds at most 4,096 members");
         for (int k = 0; k < 3; ++k)
             if (!(half_extent[k] > 0.f) || !isfinite(half_extent[k]))
                 return fail(VF_EINVAL, "vf_set_swarms: half extents must be > 0");
@@ -674,20 +710,32 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
         ctx->swarm = SwarmTable{};
         ctx->swarm_bytes = 0;
     }
+    for (auto& tr : ctx->swarm_trees) ctx_free(ctx, tr.block, tr.bytes);
+    ctx->swarm_trees.clear();
+    ctx->swarm_members = 0;
+    ctx->swarm_nodes = 0;
+    ++ctx->swarm_gen;
     if (n_swarms == 0) return VF_OK;
-    const int64_t off_bytes = (int64_t)(n_swarms + 1) * 4;
-    const int64_t bytes = ((off_bytes + 255) / 256) * 256 + std::max<int64_t>(total, 1) * 4;
+    // first node of each swarm's tree
+    std::vector<int32_t> node_off((size_t)n_swarms + 1, 0);
+    for (int32_t s = 0; s < n_swarms; ++s) node_off[s + 1] = node_off[s] + swarm_tree_nodes(offsets[s + 1] - offsets[s]);
+    const int64_t off_bytes = ((int64_t)(n_swarms + 1) * 4 + 255) / 256 * 256;
+    const int64_t slot_bytes = (std::max<int64_t>(total, 1) * 4 + 255) / 256 * 256;
+    const int64_t bytes = 2 * off_bytes + slot_bytes;
     void* p = nullptr;
     vf_status st = ctx_alloc(ctx, &p, bytes);
     if (st != VF_OK) return st;
     char* base = (char*)p;
     int32_t* d_off = (int32_t*)base;
-    int32_t* d_slots = (int32_t*)(base + ((off_bytes + 255) / 256) * 256);
-    VF_HIP(hipMemcpy(d_off, offsets, off_bytes, hipMemcpyHostToDevice));
+    int32_t* d_node_off = (int32_t*)(base + off_bytes);
+    int32_t* d_slots = (int32_t*)(base + 2 * off_bytes);
+    VF_HIP(hipMemcpy(d_off, offsets, (size_t)(n_swarms + 1) * 4, hipMemcpyHostToDevice));
+    VF_HIP(hipMemcpy(d_node_off, node_off.data(), (size_t)(n_swarms + 1) * 4, hipMemcpyHostToDevice));
     if (total > 0) VF_HIP(hipMemcpy(d_slots, slots, total * 4, hipMemcpyHostToDevice));
     SwarmTable t{};
     t.off = d_off;
     t.slots = d_slots;
+    t.node_off = d_node_off;
     t.n = n_swarms;
     double r2 = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -698,6 +746,8 @@ vf_status vf_set_swarms(vf_ctx* ctx, int32_t n_swarms, const int32_t* offsets, c
     for (int k = 0; k < 3; ++k) t.rgb[k] = rgb[k];
     ctx->swarm = t;
     ctx->swarm_bytes = bytes;
+    ctx->swarm_members = total;
+    ctx->swarm_nodes = node_off[n_swarms];
     return VF_OK;
 }
 

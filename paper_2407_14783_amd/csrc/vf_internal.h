@@ -64,6 +64,7 @@ constexpr int kMaxBvhDepth = kWidth == 4 ? 40 : 18;
 // a packet keeps at most kWidth - 1 pending siblings per level of its path plus the children just pushed
 static_assert((kWidth - 1) * (kMaxBvhDepth - 1) + kWidth <= kStackCap, "traversal stack cannot overflow");
 constexpr int kMaxScenes = 1024;
+constexpr int kServerMaxAttempts = 8;   // batches a server request may be launched in before it fails
 constexpr int kMaxImage = 1024;
 
 // sticky device error bits
@@ -165,14 +166,58 @@ bool check_noise(const vf_noise& c, std::string* why);
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
-// Swarm table: CSR lists of member state slots and the members' body box.
+// One swarm member in its swarm's tree order (64 bytes: one 16-dword scalar load).
+struct alignas(16) SwarmMember {
+    float r[9];       // R(q / |q|) of the member's state, row major (float32, as the render tests it)
+    float c[3];       // the member's position (box centre)
+    int32_t j;        // index in the swarm's slot list: the member's id is n_tris + j
+    int32_t slot;     // its state slot (a view does not see its own agent)
+    int32_t pad[2];
+};
+static_assert(sizeof(SwarmMember) == 64, "swarm member record is 64 bytes");
+constexpr int kSwarmMaxMembers = 4096;   // members per swarm (the tree build sorts them in LDS)
+
+// Swarm table: CSR lists of member state slots, the members' body box, and the members' trees of the
+// launch (per stream; rebuilt from the states before every render that shows swarms).
 struct SwarmTable {
-    const int32_t* off;     // [n + 1]
-    const int32_t* slots;   // [off[n]]
+    const int32_t* off;       // [n + 1]
+    const int32_t* slots;     // [off[n]]
+    const int32_t* node_off;  // [n + 1] first node of each swarm's tree
     int32_t n;
     float half[3];
-    float radius;           // |half|, the bounding-sphere radius used by the collision check
+    float radius;             // |half|, the bounding-sphere radius used by the collision check
     uint8_t rgb[4];
+    Node4* nodes;             // trees, node_off[n] nodes
+    SwarmMember* members;     // members in tree order, swarm s at off[s]
+};
+// Nodes of the implicit tree over m members (four per leaf, four children per node).
+__host__ __device__ inline int32_t swarm_tree_levels(int32_t m) {
+    const int32_t groups = (m + 3) / 4;
+    int32_t levels = 1;
+    for (int64_t span = 4; span < groups; span *= 4) ++levels;
+    return levels;
+}
+__host__ __device__ inline int32_t swarm_level_nodes(int32_t m, int32_t levels, int32_t d) {
+    // level d (0 = root) of a tree of `levels` levels: each node of the lowest level holds four leaves
+    const int64_t groups = (m + 3) / 4;
+    int64_t span = 1;
+    for (int32_t k = d; k < levels; ++k) span *= 4;
+    return (int32_t)((groups + span - 1) / span);
+}
+__host__ __device__ inline int32_t swarm_tree_nodes(int32_t m) {
+    if (m <= 0) return 0;
+    const int32_t levels = swarm_tree_levels(m);
+    int32_t total = 0;
+    for (int32_t d = 0; d < levels; ++d) total += swarm_level_nodes(m, levels, d);
+    return total;
+}
+
+// Member trees of one stream's launches (nodes, then member records), for one vf_set_swarms generation.
+struct SwarmTree {
+    void* stream = nullptr;
+    void* block = nullptr;
+    int64_t bytes = 0;
+    int64_t gen = -1;
 };
 
 struct SceneHost {
@@ -227,6 +272,10 @@ struct vf_ctx {
     std::vector<vf::Counters> counters;
     vf::SwarmTable swarm{};                // device copy of the swarm lists (n = 0: none)
     int64_t swarm_bytes = 0;
+    int64_t swarm_members = 0;             // members over all swarms
+    int64_t swarm_nodes = 0;               // tree nodes over all swarms
+    int64_t swarm_gen = 0;                 // bumped by every vf_set_swarms
+    std::list<vf::SwarmTree> swarm_trees;  // per stream: the member trees of its launches
     bool timing = false;                   // events around every render launch
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;   // recorded pairs
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_free;     // reusable pairs
@@ -300,8 +349,7 @@ struct StepBackArgs {
     const float* grad_out;
     float* grad_in;
     float* grad_action;
-    DynConst dyn;        // the adjoint linearises in float32
-    DynConstD dynd;      // forward sub-steps recomputed as the step computed them
+    DynConstD dyn;       // the step's FP64 constants (the adjoint recomputes and linearises its sub-steps)
 };
 struct RenderBackArgs {
     const SceneDesc* scenes;
@@ -384,8 +432,11 @@ hipError_t launch_closest_point(const QueryArgs& q, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, hipStream_t st);
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, bool noise, hipStream_t st);
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);
+hipError_t launch_swarm_tree(const SwarmTable& sw, const float* state, int64_t n_slots, uint32_t* err,
+                             hipStream_t st);
 hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st);
 hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n, float* out, hipStream_t st);
+hipError_t launch_scatter_rows(float* state, const int32_t* idx, int32_t n, const float* rows, hipStream_t st);
 vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t* tris, int32_t nt,
                       const uint8_t* rgb, hipStream_t st, SceneHost* out);
 

@@ -37,7 +37,8 @@ class RequestOut(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_int64), ("agents", ctypes.c_int64), ("requests", ctypes.c_int64),
                 ("max_batch_agents", ctypes.c_int64), ("pending", ctypes.c_int64),
-                ("in_flight_batches", ctypes.c_int64)]
+                ("in_flight_batches", ctypes.c_int64), ("requeued", ctypes.c_int64),
+                ("failed_batches", ctypes.c_int64)]
 
 
 _P, _I64 = ctypes.c_void_p, ctypes.c_int64
@@ -48,8 +49,9 @@ lib.vf_server_poll.argtypes = [_P, _I64, ctypes.POINTER(ctypes.c_int32)]
 lib.vf_server_wait.argtypes = [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]
 lib.vf_server_stats_get.argtypes = [_P, ctypes.POINTER(ServerStats)]
 lib.vf_server_destroy.argtypes = [_P]
+lib.vf_server_inject_faults.argtypes = [_P, _I64]
 for _f in ("vf_server_create", "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get",
-           "vf_server_destroy"):
+           "vf_server_destroy", "vf_server_inject_faults"):
     getattr(lib, _f).restype = ctypes.c_int32
 
 
@@ -133,6 +135,10 @@ class Server:
         check(lib.vf_server_wait(self.h, ticket, p(depth), p(ids), p(rgb), p(st), ctypes.byref(lat)), "vf_server_wait")
         return {"depth": depth, "tri_id": ids, "rgb": rgb, "state": st, "latency_s": lat.value}
 
+    def inject_faults(self, n):
+        """Treat the next n batches that finish as failed (restored and run again)."""
+        check(lib.vf_server_inject_faults(self.h, int(n)), "vf_server_inject_faults")
+
     def stats(self):
         s = ServerStats()
         check(lib.vf_server_stats_get(self.h, ctypes.byref(s)), "vf_server_stats_get")
@@ -148,20 +154,30 @@ class Server:
 # load generation
 # ---------------------------------------------------------------------------
 
-def make_requests(seed, n_requests, n_scenes, slots_per_scene, params, sizes=((64, 64), (96, 96))):
-    """Seeded request mix: n_env = floor(exp(U(0, ln 1025))) in [1, 1024], uniform scene and size,
-    distinct random slots of that scene, CTBR actions as in the batched workloads."""
+def make_requests(seed, n_requests, n_scenes, slots_per_scene, params, sizes=((64, 64), (96, 96)), slots="window"):
+    """Seeded request mix: n_env = floor(exp(U(0, ln 1025))) in [1, 1024], uniform scene and size, CTBR
+    actions as in the batched workloads.  slots: "window" gives each scene's requests the next n_env of its
+    env slots in turn (wrapping), as clients that each own their environments would: requests in flight
+    together touch distinct slots until a scene's 4,096 slots wrap.  "random" draws distinct random slots
+    of the scene for every request, so two requests of one scene almost always share a slot and are
+    stepped one after the other."""
     rng = np.random.default_rng(seed)
     reqs = []
+    cursor = [0] * n_scenes
     for _ in range(n_requests):
         n_env = int(min(1024, slots_per_scene, max(1, math.floor(math.exp(rng.uniform(0.0, math.log(1025.0)))))))
         sc = int(rng.integers(0, n_scenes))
         hw = sizes[int(rng.integers(0, len(sizes)))]
-        slots = sc * slots_per_scene + rng.choice(slots_per_scene, size=n_env, replace=False)
+        if slots == "window":
+            local = (cursor[sc] + np.arange(n_env)) % slots_per_scene
+            cursor[sc] = (cursor[sc] + n_env) % slots_per_scene
+        else:
+            local = rng.choice(slots_per_scene, size=n_env, replace=False)
+        slots_ = sc * slots_per_scene + local
         acts = np.empty((n_env, 4), dtype=np.float32)
         acts[:, 0] = rng.uniform(0.5, 2.0, n_env) * params["g"]
         acts[:, 1:] = rng.uniform(-3.0, 3.0, (n_env, 3))
-        reqs.append((sc, hw, slots.astype(np.int32), acts))
+        reqs.append((sc, hw, slots_.astype(np.int32), acts))
     return reqs
 
 
@@ -269,19 +285,24 @@ def bench_summary(sim_ctx, params, n_requests=4000, seed=7, n_streams=3):
     reqs = make_requests(seed, n_requests, 8, per, params)
     mean_env = float(np.mean([r[2].shape[0] for r in reqs]))
     ring = torch.empty(256 << 20 >> 2, dtype=torch.float32, device="cuda")     # 256 MiB of depth outputs
-    lat, wall, frames = run_load(server, sids, reqs[:min(1500, n_requests)], rate=None, device_out=ring)
+    lat, wall, frames = run_load(server, sids, reqs[:min(2000, n_requests)], rate=None, device_out=ring)
     sat_fps = frames / wall
-    lam_sat = sat_fps / mean_env
+    lam_server = sat_fps / mean_env
+    lam_plain = plain_fps / mean_env        # the plain batched step's rate in requests of the mix
     out = {"workload": "8 room-graph scenes (20k-2M triangles), 4,096 resident env slots each, requests of "
-                       "1-1,024 envs (log-uniform), 64x64 or 96x96, one step + render each, depth delivered "
-                       "to a device buffer",
+                       "1-1,024 envs (log-uniform), 64x64 or 96x96, one step + render each, each scene's requests "
+                       "on the scene's next env slots in turn, depth delivered to a device buffer",
            "requests_per_rate": n_requests, "mean_envs_per_request": mean_env,
            "plain_batched_frames_per_s": plain_fps, "saturated_frames_per_s": sat_fps,
-           "saturated_requests_per_s": lam_sat, "rates": []}
-    for frac in (0.25, 0.5, 0.9):
-        lat, wall, frames = run_load(server, sids, reqs, rate=frac * lam_sat, seed=int(frac * 100), device_out=ring)
-        out["rates"].append({"load": frac, "requests_per_s": frac * lam_sat, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "frames_per_s": frames / wall})
+           "saturated_fraction_of_plain": sat_fps / plain_fps,
+           "lambda_sat_plain_requests_per_s": lam_plain, "saturated_requests_per_s": lam_server,
+           "rates": [], "rates_of_server_saturation": []}
+    for key, lam in (("rates", lam_plain), ("rates_of_server_saturation", lam_server)):
+        for frac in (0.25, 0.5, 0.9):
+            lat, wall, frames = run_load(server, sids, reqs, rate=frac * lam, seed=int(frac * 100), device_out=ring)
+            out[key].append({"load": frac, "requests_per_s": frac * lam, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                             "p99_ms": float(np.percentile(lat, 99) * 1e3), "frames_per_s": frames / wall,
+                             "offered_frames_per_s": frac * lam * mean_env})
     out["server_stats"] = server.stats()
     server.close()
     for s in sids:

@@ -315,7 +315,7 @@ class Context:
         out = (ctypes.c_uint64 * 12)()
         check(lib.vf_stats_read(self.h, out, 1 if reset else 0), "vf_stats_read")
         keys = ("rays", "node_lane", "box_lane", "tri_lane", "node_wave", "tri_wave", "box_ops", "hits",
-                "need_node", "need_box", "need_tri", "reserved")
+                "need_node", "need_box", "need_tri", "member_tests")
         return dict(zip(keys, list(out)))
 
     def mem_usage(self):

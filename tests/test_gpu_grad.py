@@ -20,7 +20,7 @@ import torch
 from oracle import dynamics as odyn
 from oracle import gradients as ograd
 from oracle import render as oren
-from workloads import agents, default_params, scenes
+from workloads import agents, default_params, device_params, scenes
 from tests.gpu_util import header, record
 
 pytestmark = pytest.mark.gpu
@@ -87,7 +87,7 @@ def test_step_backward_matches_fd_jacobian(vf, variant):
     header(f"step_backward: {variant}")
     ctx.step_backward(p, _dev(s), _dev(a), _dev(lam), g_in, g_a)
     torch.cuda.synchronize()
-    js, ja = ograd.step_jacobian(s.astype(np.float64), a.astype(np.float64), p)
+    js, ja = ograd.step_jacobian(s.astype(np.float64), a.astype(np.float64), device_params(p))
     ref_in = np.einsum("nij,ni->nj", js, lam.astype(np.float64))
     ref_a = np.einsum("nij,ni->nj", ja, lam.astype(np.float64))
     gi, ga = g_in.cpu().numpy(), g_a.cpu().numpy()
@@ -203,7 +203,8 @@ def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
     sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
     header(f"BPTT: 4 agents x 64 steps, k = 8, w_goal = {w_goal}, {N_DIRECTIONS} directions")
     loss, g_s0, g_a = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal)
-    l_ref = ograd.rollout_loss(s0, acts, p, sc, goals, VIEW64, w_goal=w_goal)
+    pd = device_params(p)      # the oracle runs on the parameter values the device receives
+    l_ref = ograd.rollout_loss(s0, acts, pd, sc, goals, VIEW64, w_goal=w_goal)
     assert abs(loss - l_ref) <= 1e-4 * abs(l_ref)
     worst, jumps = 0.0, []
     for j in range(N_DIRECTIONS):
@@ -211,7 +212,7 @@ def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
         u_a = rng.normal(size=acts.shape)
         norm = math.sqrt((u_s ** 2).sum() + (u_a ** 2).sum())
         u_s, u_a = u_s / norm, u_a / norm
-        fd, smooth, fd_c, n_jumps, jumped = ograd.rollout_directional(s0, acts, p, sc, goals, VIEW64, u_s, u_a,
+        fd, smooth, fd_c, n_jumps, jumped = ograd.rollout_directional(s0, acts, pd, sc, goals, VIEW64, u_s, u_a,
                                                                       h=1e-6, w_goal=w_goal, return_jumps=True)
         if n_jumps:
             _, gs, ga = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal, keep=~jumped)
@@ -247,7 +248,8 @@ def test_bptt_coordinates_vs_oracle_fd(vf, agent):
     header(f"BPTT coordinates: agent {agent}, {sc['tris'].shape[0]} triangles, 64 steps")
     loss, g_s0, g_a = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, w_goal)
     # FP64 oracle states s_k (dynamics only) to start the differences at step k from
-    traj = odyn.rollout(s0.astype(np.float64), acts.astype(np.float64), p)
+    pd = device_params(p)      # the oracle runs on the parameter values the device receives
+    traj = odyn.rollout(s0.astype(np.float64), acts.astype(np.float64), pd)
     groups = [("a0", 0), ("a31", 31), ("a63", 63), ("s0", None)]
     worst = 0.0
     n_checked = 0
@@ -263,7 +265,7 @@ def test_bptt_coordinates_vs_oracle_fd(vf, agent):
             else:
                 u_a[0, 0, c] = 1.0
             fd, smooth, fd_c, n_jumps, jumped = ograd.rollout_directional(
-                traj[start], acts[start:], p, sc, goals, VIEW64, u_s, u_a, h=1e-6, w_goal=w_goal,
+                traj[start], acts[start:], pd, sc, goals, VIEW64, u_s, u_a, h=1e-6, w_goal=w_goal,
                 return_jumps=True)
             if n_jumps:
                 keep = np.ones((H, 1, 4096), dtype=bool)

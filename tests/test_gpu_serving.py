@@ -226,3 +226,37 @@ def test_poisson_load_latency(setup):
     header(f"serving: {len(reqs)} Poisson requests, p50 {np.percentile(lat, 50) * 1e3:.2f} ms, "
            f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms, {frames / wall:.0f} frames/s")
     assert lat.shape[0] == len(reqs) and np.all(lat > 0) and np.all(np.isfinite(lat))
+
+
+def test_backend_errors_requeue_and_change_no_result(setup):
+    """Host-forced backend errors: the first batches to finish are reported failed, their env slots are
+    restored from the snapshot taken before their step and their requests run again.  Every result, and
+    the state table at the end, equals a server run without the errors; requests sharing slots still
+    take effect in submission order."""
+    env = setup
+    rng = np.random.default_rng(23)
+    reqs = []
+    for k in range(36):
+        sc = int(rng.integers(0, 3))
+        n_env = int(rng.integers(1, 60))
+        slots = (sc * PER + rng.choice(PER, size=n_env, replace=False)).astype(np.int32)   # slots overlap
+        acts = agents.random_actions(300 + k, 1, n_env, env["p"])[0]
+        reqs.append((sc, [(64, 64), (96, 96), (40, 56)][k % 3], slots, acts))
+    runs = []
+    for faults in (0, 5):
+        st = torch.as_tensor(env["table"]).cuda()
+        srv = _server(env, st)
+        srv.inject_faults(faults)
+        header(f"serving: 36 requests with {faults} host-forced batch failures")
+        tickets = [srv.submit(env["sids"][r[0]], r[1], r[2], r[3]) for r in reqs]
+        res = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+        srv.close()
+        runs.append((res, st.cpu().numpy(), stats))
+    (clean, st_clean, s_clean), (faulty, st_faulty, s_faulty) = runs
+    assert s_clean["failed_batches"] == 0 and s_faulty["failed_batches"] == 5
+    assert s_faulty["requeued"] >= 5
+    assert np.array_equal(st_clean, st_faulty)
+    for a, b in zip(clean, faulty):
+        for key in ("depth", "tri_id", "rgb", "state"):
+            assert np.array_equal(a[key], b[key]), key

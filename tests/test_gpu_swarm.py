@@ -15,7 +15,7 @@ import torch
 from oracle import dynamics as odyn
 from oracle import render as oren
 from workloads import agents, default_params, device_params, scenes
-from tests.gpu_util import compare_render, header
+from tests.gpu_util import compare_render, header, record
 
 pytestmark = pytest.mark.gpu
 
@@ -143,3 +143,71 @@ def test_swarm_step_and_collision(vf):
             assert col[i] == (expect <= radius)
     ctx.set_swarms([])
     ctx.free_scene(sid)
+
+
+def _swarm_of_100(p, rng, n=100):
+    """n drones on a jittered 5 x 5 x 4 lattice in the box room, attitudes near level."""
+    g = np.stack(np.meshgrid(np.arange(5), np.arange(5), np.arange(4), indexing="ij"), -1).reshape(-1, 3)[:n]
+    pos = np.array([2.0, 2.0, 0.8]) + g * np.array([1.5, 1.5, 0.8]) + rng.uniform(-0.3, 0.3, (n, 3))
+    q = rng.normal(size=(n, 4))
+    q[:, 1:4] *= 0.3
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return agents.make_states(pos, p, quat=q)
+
+
+def test_swarm_of_100_through_the_tree(vf):
+    """A swarm of 100 members (the paper's 100-drone example): every member's 32x32 view against the
+    oracle's brute-force render of the mesh and the 99 other boxes, before and after three steps (the
+    tree is rebuilt from the new states); member tests per ray with the tree against the 99 without."""
+    sim, ctx = vf
+    p = default_params()
+    sc = scenes.box_room(seed=1)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    n_tris = sc["tris"].shape[0]
+    rng = np.random.default_rng(100)
+    n = 100
+    st0 = _swarm_of_100(p, rng, n)
+    groups = [list(range(n))]
+    ctx.set_swarms(groups, half_extent=HALF, rgb=RGB)
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (32, 32), swarm=0)
+    st = torch.as_tensor(st0).cuda()
+    depth = torch.empty(npx).cuda()
+    ids = torch.empty(npx, dtype=torch.int32).cuda()
+    acts = agents.random_actions(9, 3, n, p, c_range=(0.95, 1.05), rate=0.5)
+    header("swarm of 100: views through the member tree, before and after 3 steps")
+    for phase in ("start", "after 3 steps"):
+        if phase != "start":
+            for k in range(3):
+                ctx.step(p, st, torch.as_tensor(acts[k]).cuda(), views=views, max_hw=(mh, mw), depth=depth,
+                         tri_id=ids, out_pixels=npx)
+        ctx.read_stats(reset=True)
+        ctx.set_stats(True)
+        ctx.render(st, views, max_hw=(mh, mw), depth=depth, tri_id=ids, out_pixels=npx)
+        ctx.set_stats(False)
+        stats = ctx.read_stats(reset=True)
+        ctx.sync_check()
+        s_now = st.cpu().numpy()
+        dd, ii = depth.cpu().numpy(), ids.cpu().numpy()
+        masked, seen = [], 0
+        for i in range(n):
+            ref = oren.render_view(s_now[i].astype(np.float64), sc, 32, 32, math.pi / 2,
+                                   others=_others(s_now, groups[0], i, n_tris))
+            sl = slice(offs[i], offs[i] + 1024)
+            masked.append(compare_render(dd[sl], ii[sl], None, ref, 100.0, label=f"{phase} agent {i}"))
+            seen += int((ii[sl] >= n_tris).sum())
+        per_ray = stats["member_tests"] / max(stats["rays"], 1)
+        record(f"swarm100[{phase}]", member_tests_per_ray=per_ray, brute_force_per_ray=n - 1,
+               member_pixels=seen, masked=float(np.mean(masked)))
+        assert np.mean(masked) < 0.02
+        assert seen > 1000, "the members should fill part of the views"
+        assert per_ray < 0.5 * (n - 1)
+    ctx.set_swarms([])
+    ctx.free_scene(sid)
+
+
+def test_swarm_limits(vf):
+    sim, ctx = vf
+    with pytest.raises(sim.capi.VfError):
+        ctx.set_swarms([list(range(4097))])
+    ctx.set_swarms([list(range(4096))])     # the largest swarm builds
+    ctx.set_swarms([])
