@@ -210,6 +210,22 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
                   const vf_view* views, int32_t max_h, int32_t max_w,
                   float* depth, int32_t* tri_id, uint8_t* rgb, int64_t out_pixels, void* stream);
 
+/* Allocation-free form of vf_step, for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, semantics and results
+ * as vf_step (bit for bit: the same kernels).  It allocates nothing and calls no allocating routine: its
+ * scratch -- the fused launch's arrival counters (one per state slot) and the cost order's per-workgroup
+ * work and workgroup order -- lives in a file-scope device array of 3 MiB, one copy per GPU, held until
+ * the process ends; vf_create looks up its address once per device.  Limits: a fused launch (small
+ * batches, or VF_LAUNCH_FUSED) takes at most 262,144 state slots (n_slots), else VF_EINVAL; the cost
+ * order covers split launches of 1,024 .. 262,144 workgroups, larger ones keep the plain order; no
+ * spatial order and no timing events; swarm mode is refused (VF_EINVAL: its member trees are allocated
+ * per stream).  Every call on a GPU shares that GPU's array and leaves its contents for the next call
+ * (the arrival counters are cleared by a fill kernel at each fused call; work estimates from another
+ * call only change the workgroup order, never a result): calls that overlap on one GPU race. */
+vf_status vf_step_noalloc(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int32_t* env_idx, float* state,
+                          int64_t n_slots, const float* action, const vf_view* views, int32_t max_h, int32_t max_w,
+                          float* depth, int32_t* tri_id, uint8_t* rgb, int64_t out_pixels, void* stream);
+
 /* Render only (the second half of vf_step) at the given states. */
 vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float* state, int64_t n_slots,
                     const vf_view* views, int32_t max_h, int32_t max_w,

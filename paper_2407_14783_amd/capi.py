@@ -27,7 +27,7 @@ EXPORTED = ("vf_create", "vf_destroy", "vf_scene_build", "vf_scene_free", "vf_sc
             "vf_sync_check", "vf_mem_usage", "vf_last_error", "vf_set_launch_mode", "vf_set_bvh_builder", "vf_set_bvh_leaf_size", "vf_server_create",
             "vf_server_submit", "vf_server_poll", "vf_server_wait", "vf_server_stats_get", "vf_server_destroy",
             "vf_closest_point", "vf_sensor_noise", "vf_scene_set_labels", "vf_segmentation", "vf_imu", "vf_collision", "vf_set_swarms", "vf_set_spatial_order", "vf_set_cost_order", "vf_set_timing", "vf_timing_read",
-            "vf_set_render_noise", "vf_server_inject_faults")
+            "vf_set_render_noise", "vf_server_inject_faults", "vf_step_noalloc")
 
 
 class DynParams(ctypes.Structure):
@@ -91,6 +91,7 @@ def _load():
         "vf_scene_info_get": ([P, I32, ctypes.POINTER(SceneInfo)], I32),
         "vf_scene_export": ([P, I32, P, I64, P, I64], I32),
         "vf_step": ([P, ctypes.POINTER(DynParams), I64, P, P, I64, P, P, I32, I32, P, P, P, I64, P], I32),
+        "vf_step_noalloc": ([P, ctypes.POINTER(DynParams), I64, P, P, I64, P, P, I32, I32, P, P, P, I64, P], I32),
         "vf_render": ([P, I64, P, P, I64, P, I32, I32, P, P, P, I64, P], I32),
         "vf_step_backward": ([P, ctypes.POINTER(DynParams), I64, P, P, P, P, P, P], I32),
         "vf_render_backward": ([P, I64, P, P, I32, I32, P, P, I64, P, P], I32),

@@ -579,6 +579,12 @@ __global__ void k_gather_rows(const float* __restrict__ state, const int32_t* __
     out[i] = state[(int64_t)idx[a] * 17 + k];
 }
 
+// p[0, n) = value (a kernel, not a memset, so the fill can be captured in a graph).
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
 // Copy rows[i] -> state row idx[i] (one thread per value): puts saved states back.
 __global__ void k_scatter_rows(float* __restrict__ state, const int32_t* __restrict__ idx, int32_t n,
                                const float* __restrict__ rows) {
@@ -591,6 +597,13 @@ __global__ void k_scatter_rows(float* __restrict__ state, const int32_t* __restr
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter_rows(float* state, const int32_t* idx, int32_t n, const float* rows, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_rows, dim3((n * 17 + 255) / 256), dim3(256), 0, st, state, idx, n, rows);

@@ -129,6 +129,38 @@ bool check_noise(const vf_noise& c, std::string* why) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free step (vf_step_noalloc): a file-scope device array, one copy per GPU,
+// held until the process ends.  Layout: the fused launch's arrival counters (one per state slot), then
+// the cost order's per-workgroup work and its workgroup order.  The host reaches it only through the
+// address hipGetSymbolAddress returns on each device (the array's name is not a device address in host
+// code).
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocSlots = 1 << 18;
+constexpr int64_t kNoAllocCost = (int64_t)kGroupOrderMax * kWavesPerBlock;
+constexpr int64_t kNoAllocWords = kNoAllocSlots + kNoAllocCost + kGroupOrderMax;
+static __device__ __align__(256) int32_t scratch[kNoAllocWords];
+
+struct NoAllocDevice {
+    int32_t* ptr = nullptr;              // this device's copy of scratch
+    int32_t cost_n = -1, cost_groups = -1;   // launch shape the work in the cost section belongs to
+};
+constexpr int kNoAllocDevices = 64;
+static std::mutex g_noalloc_mu;
+static NoAllocDevice g_noalloc[kNoAllocDevices];
+
+// Once per device, with that device current: the device address of its scratch.
+static vf_status noalloc_setup(int device) {
+    if (device >= kNoAllocDevices) return fail(VF_EINVAL, "vf_create: device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc[device].ptr) return VF_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_noalloc[device].ptr = (int32_t*)p;
+    return VF_OK;
+}
+
 static vf_status sync_scene_table(vf_ctx* ctx) {
     std::vector<SceneDesc> tab(kMaxScenes);
     std::vector<const int32_t*> lab(kMaxScenes, nullptr);
@@ -205,6 +237,12 @@ vf_status vf_create(int device, size_t hbm_budget_bytes, vf_ctx** out) {
     if (hipMemset(p, 0, 256) != hipSuccess || sync_scene_table(ctx) != VF_OK) {
         vf_destroy(ctx);
         return fail(VF_EHIP, "vf_create: device initialisation failed");
+    }
+    s = noalloc_setup(device);
+    if (s != VF_OK) {
+        const std::string why = vf_last_error(nullptr);
+        vf_destroy(ctx);
+        return fail(s, why);
     }
     *out = ctx;
     return VF_OK;
@@ -506,6 +544,69 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     a.counters = counters;
     a.dyn = dc;
     VF_HIP(timed_render(ctx, a, true, st));
+    return VF_OK;
+}
+
+vf_status vf_step_noalloc(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int32_t* env_idx, float* state,
+                          int64_t n_slots, const float* action, const vf_view* views, int32_t max_h, int32_t max_w,
+                          float* depth, int32_t* tri_id, uint8_t* rgb, int64_t out_pixels, void* stream) {
+    vf_status s = check_render_common(ctx, n, state, n_slots, views, max_h, max_w, depth, tri_id, rgb, out_pixels,
+                                      "vf_step_noalloc");
+    if (s != VF_OK) return s;
+    if (!params) return fail(VF_EINVAL, "vf_step_noalloc: params is NULL");
+    if (n > 0 && !action) return fail(VF_EINVAL, "vf_step_noalloc: action is NULL");
+    std::string why;
+    if (!check_dyn_params(*params, &why)) return fail(VF_EINVAL, "vf_step_noalloc: " + why);
+    if (n == 0) return VF_OK;
+    NoAllocDevice& nd = g_noalloc[ctx->device];
+    if (!nd.ptr) return fail(VF_EHIP, "vf_step_noalloc: the device's scratch address is not known");
+    if (views && ctx->swarm.n > 0)
+        return fail(VF_EINVAL, "vf_step_noalloc: swarm mode needs the per-stream member trees vf_step allocates");
+    VF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    DynConstD dc = make_dyn_const_d(*params);
+    if (!views) {
+        StepArgs a{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
+        VF_HIP(launch_step(a, st));
+        return VF_OK;
+    }
+    RenderArgs a = make_render_args(ctx, n, env_idx, state, n_slots, views, max_h, max_w, depth, tri_id, rgb,
+                                    out_pixels);
+    const int32_t gpa = render_groups_per_agent(max_h, max_w);
+    const int64_t total = n * (int64_t)gpa;
+    const bool split = ctx->launch_mode == VF_LAUNCH_SPLIT || (ctx->launch_mode == VF_LAUNCH_AUTO && total > 1024);
+    if (split) {
+        StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
+        VF_HIP(launch_step(sa, st));
+        // the cost order on the scratch's work and order sections (launches of kGroupOrderMin ..
+        // kGroupOrderMax workgroups; the first launch of a shape on the device records the work)
+        if (ctx->cost_order && total >= kGroupOrderMin && total <= kGroupOrderMax) {
+            bool have_cost;
+            {
+                std::lock_guard<std::mutex> lk(g_noalloc_mu);
+                have_cost = nd.cost_n == (int32_t)n && nd.cost_groups == gpa;
+                nd.cost_n = (int32_t)n;
+                nd.cost_groups = gpa;
+            }
+            a.cost = nd.ptr + kNoAllocSlots;
+            if (have_cost) {
+                int32_t* perm = a.cost + kNoAllocCost;
+                GroupOrderArgs g{(int32_t)total, a.cost, perm};
+                VF_HIP(launch_group_order(g, st));
+                a.group_order = perm;
+            }
+        }
+        VF_HIP(launch_render(a, false, ctx->stats, ctx->render_noise_on, st));
+        return VF_OK;
+    }
+    if (n_slots > kNoAllocSlots)
+        return fail(VF_EINVAL, "vf_step_noalloc: a fused launch takes at most 262,144 state slots (the scratch's "
+                               "arrival counters); use a split launch or vf_step");
+    VF_HIP(launch_fill_i32(nd.ptr, n_slots, 0, st));     // the arrival counters start at zero
+    a.action = action;
+    a.counters = nd.ptr;
+    a.dyn = dc;
+    VF_HIP(launch_render(a, true, ctx->stats, ctx->render_noise_on, st));
     return VF_OK;
 }
 

@@ -437,6 +437,7 @@ hipError_t launch_swarm_tree(const SwarmTable& sw, const float* state, int64_t n
 hipError_t launch_render_backward(const RenderBackArgs& a, hipStream_t st);
 hipError_t launch_gather_rows(const float* state, const int32_t* idx, int32_t n, float* out, hipStream_t st);
 hipError_t launch_scatter_rows(float* state, const int32_t* idx, int32_t n, const float* rows, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t st);
 vf_status build_scene(vf_ctx* ctx, const float* verts, int64_t nv, const int32_t* tris, int32_t nt,
                       const uint8_t* rgb, hipStream_t st, SceneHost* out);
 

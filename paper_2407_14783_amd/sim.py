@@ -130,6 +130,20 @@ class Context:
                           _ptr(views), int(max_hw[0]), int(max_hw[1]), _ptr(depth), _ptr(tri_id), _ptr(rgb),
                           int(out_pixels), _stream(stream)), "vf_step")
 
+    def step_noalloc(self, params, state, action, views=None, env_idx=None, max_hw=(0, 0), depth=None, tri_id=None,
+                     rgb=None, out_pixels=0, stream=None):
+        """vf_step_noalloc: step() with no device allocation (scratch in the library's per-GPU array)."""
+        p = params if isinstance(params, capi.DynParams) else capi.params_struct(params)
+        n = action.shape[0]
+        _check_views(views, n)
+        if env_idx is not None and env_idx.numel() < n:
+            raise ValueError("env_idx holds fewer than n entries")
+        if env_idx is None:
+            _check_rows(state, n, 17, "state")
+        check(lib.vf_step_noalloc(self.h, ctypes.byref(p), n, _ptr(env_idx), _ptr(state), state.shape[0],
+                                  _ptr(action), _ptr(views), int(max_hw[0]), int(max_hw[1]), _ptr(depth),
+                                  _ptr(tri_id), _ptr(rgb), int(out_pixels), _stream(stream)), "vf_step_noalloc")
+
     def render(self, state, views, n=None, env_idx=None, max_hw=(64, 64), depth=None, tri_id=None, rgb=None,
                out_pixels=0, stream=None):
         n = state.shape[0] if n is None else n
