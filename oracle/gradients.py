@@ -42,8 +42,26 @@ def central_difference(fun, x, direction, h=1e-6):
     return (fun(x + h * u) - fun(x - h * u)) / (2.0 * h)
 
 
+def rollout_edge_mask(state0, actions, params, scene, view, eps_edge=1e-4):
+    """Pixel-steps [H, N, pixels] of the rollout from state0 whose closest hit is not decided robustly:
+    the comparison mask of render_view (edges, near misses, ties, clip planes) with eps_edge.  At a
+    triangle edge the depth stays continuous but its derivative jumps from one plane to the other, and
+    which plane a ray in finite precision meets there is not decided: the gradient of such a pixel is
+    not defined to compare."""
+    s = np.asarray(state0, dtype=np.float64)
+    masks = []
+    for a in np.asarray(actions, dtype=np.float64):
+        s = dynamics.step(s, a, params)
+        for i in range(s.shape[0]):
+            r = render.render_view(s[i], scene, view["H"], view["W"], view["hfov"], view["near"], view["far"],
+                                   view.get("miss_depth"), eps_edge=eps_edge)
+            masks.append(r["mask"].reshape(-1))
+    n = s.shape[0]
+    return np.stack(masks).reshape(-1, n, masks[0].size) if masks else np.zeros((0, n, 0), dtype=bool)
+
+
 def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_actions, h=1e-6, d0=1.0,
-                        w_goal=0.01, jump_abs=1e-2, jump_rel=1e-3, return_jumps=False):
+                        w_goal=0.01, jump_abs=1e-2, jump_rel=1e-3, return_jumps=False, remove=None):
     """Directional derivative of the rollout loss along (u_state, u_actions) by central differences.
 
     Returns (derivative, smooth, corrected, n_jumps).  The loss is piecewise
@@ -55,7 +73,8 @@ def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_
     loss restricted to the pixels that stay on one smooth branch (a change of hit
     triangle across a shared edge keeps the depth continuous and is kept).  With return_jumps the flags
     of the removed pixel-steps come back too, [H, N, pixels] (step, agent, pixel), so that the gradient
-    being checked can be taken of the same restricted loss.
+    being checked can be taken of the same restricted loss.  remove [H, N, pixels] (say rollout_edge_mask)
+    names more pixel-steps to leave out the same way; they are counted and returned with the jumped ones.
     """
     s0 = np.asarray(state0, dtype=np.float64)
     a = np.asarray(actions, dtype=np.float64)
@@ -67,6 +86,8 @@ def rollout_directional(state0, actions, params, scene, goals, view, u_state, u_
     if dp.size == 0:
         return (raw, True, raw, 0, np.zeros((0,), dtype=bool)) if return_jumps else (raw, True, raw, 0)
     jumped = np.abs(dp - dm) > jump_abs + jump_rel * np.minimum(np.abs(dp), np.abs(dm))
+    if remove is not None:
+        jumped = jumped | np.asarray(remove, dtype=bool).reshape(jumped.shape)
     n_pix = dp[0].size
     cp = float(np.sum(np.exp(-dp[jumped] / d0)) / n_pix)
     cm = float(np.sum(np.exp(-dm[jumped] / d0)) / n_pix)

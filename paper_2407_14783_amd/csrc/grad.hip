@@ -10,7 +10,7 @@
 // rotor lag (Eq. 4), the square root, the clamp (zero gradient when clamped)
 // and the CTBR mixer / rate controller.
 //
-// k_render_backward: depth t = n.(V0 - o) / n.d on the hit triangle's plane;
+// k_render_backward (in FP64): depth t = n.(V0 - o) / n.d on the hit triangle's plane;
 // dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B with d_B = R_m d_cam and
 // o = p + R t_m for a camera mounted at (R_m, t_m).  Per agent the pixel
 // sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix) are reduced in
@@ -311,20 +311,26 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     }
     const SceneDesc sc = a.scenes[vw.scene_id];
     const float* st = a.state + (int64_t)agent * 17;
-    float q[4] = {st[3], st[4], st[5], st[6]};
-    float rot[9];
-    quat_rot(q, rot);
+    const double qd[4] = {st[3], st[4], st[5], st[6]};
+    double rot[9];
+    body_rot(qd, rot);
     // camera mount: origin p + R t_m, body-frame direction R_m d_cam
-    float m[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-    if (!(vw.mount_q[1] == 0.0f && vw.mount_q[2] == 0.0f && vw.mount_q[3] == 0.0f)) quat_rot(vw.mount_q, m);
-    const float tm[3] = {vw.mount_t[0], vw.mount_t[1], vw.mount_t[2]};
-    float o[3];
-    for (int i = 0; i < 3; ++i) o[i] = st[i] + (rot[3 * i] * tm[0] + rot[3 * i + 1] * tm[1] + rot[3 * i + 2] * tm[2]);
-    const float tan_h = tanf(0.5f * vw.hfov);
+    double m[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    if (!(vw.mount_q[1] == 0.0f && vw.mount_q[2] == 0.0f && vw.mount_q[3] == 0.0f)) {
+        const double mq[4] = {vw.mount_q[0], vw.mount_q[1], vw.mount_q[2], vw.mount_q[3]};
+        body_rot(mq, m);
+    }
+    const double tm[3] = {vw.mount_t[0], vw.mount_t[1], vw.mount_t[2]};
+    double o[3];
+    for (int i = 0; i < 3; ++i)
+        o[i] = (double)st[i] + (rot[3 * i] * tm[0] + rot[3 * i + 1] * tm[1] + rot[3 * i + 2] * tm[2]);
+    const double tan_h = tan(0.5 * (double)vw.hfov);
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     uint32_t bad = 0;
     const int npix = vw.H * vw.W;
+    // every pixel's terms in FP64: the pixel sums cancel to a small fraction of their terms for some
+    // directions (a roll turns one half of the image nearer and the other farther)
     for (int pix = threadIdx.x; pix < npix; pix += kBackThreads) {
         int64_t at = vw.out_offset + pix;
         int32_t id = a.tri_id[at];
@@ -336,20 +342,23 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
         }
         const Tri tr = sc.tris[sc.sorted_of[id]];
         int r = pix / vw.W, cc = pix - r * vw.W;
-        float u = (2.0f * ((float)cc + 0.5f) / (float)vw.W - 1.0f) * tan_h;
-        float v = (1.0f - 2.0f * ((float)r + 0.5f) / (float)vw.H) * tan_h * ((float)vw.H / (float)vw.W);
-        float db[3] = {m[0] - m[1] * u + m[2] * v, m[3] - m[4] * u + m[5] * v, m[6] - m[7] * u + m[8] * v};
-        float d[3] = {rot[0] * db[0] + rot[1] * db[1] + rot[2] * db[2], rot[3] * db[0] + rot[4] * db[1] + rot[5] * db[2],
-                      rot[6] * db[0] + rot[7] * db[1] + rot[8] * db[2]};
-        float n[3] = {tr.e1y * tr.e2z - tr.e1z * tr.e2y, tr.e1z * tr.e2x - tr.e1x * tr.e2z,
-                      tr.e1x * tr.e2y - tr.e1y * tr.e2x};
-        float nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
-        if (nd == 0.0f) continue;
-        float t = (n[0] * (tr.v0x - o[0]) + n[1] * (tr.v0y - o[1]) + n[2] * (tr.v0z - o[2])) / nd;
-        const double s_o = -(double)g / (double)nd, s_d = -(double)g * (double)t / (double)nd;
-        for (int k = 0; k < 3; ++k) acc[k] += s_o * (double)n[k];
+        const double u = (2.0 * ((double)cc + 0.5) / (double)vw.W - 1.0) * tan_h;
+        const double v = (1.0 - 2.0 * ((double)r + 0.5) / (double)vw.H) * tan_h * ((double)vw.H / (double)vw.W);
+        const double db[3] = {m[0] - m[1] * u + m[2] * v, m[3] - m[4] * u + m[5] * v, m[6] - m[7] * u + m[8] * v};
+        const double d[3] = {rot[0] * db[0] + rot[1] * db[1] + rot[2] * db[2],
+                             rot[3] * db[0] + rot[4] * db[1] + rot[5] * db[2],
+                             rot[6] * db[0] + rot[7] * db[1] + rot[8] * db[2]};
+        const double e1[3] = {tr.e1x, tr.e1y, tr.e1z}, e2[3] = {tr.e2x, tr.e2y, tr.e2z};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+        if (nd == 0.0) continue;
+        const double t = (n[0] * ((double)tr.v0x - o[0]) + n[1] * ((double)tr.v0y - o[1]) +
+                          n[2] * ((double)tr.v0z - o[2])) / nd;
+        const double s_o = -(double)g / nd, s_d = -(double)g * t / nd;
+        for (int k = 0; k < 3; ++k) acc[k] += s_o * n[k];
         for (int i2 = 0; i2 < 3; ++i2)
-            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * (double)n[i2] * (double)db[j];
+            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * n[i2] * db[j];
     }
     if (bad) atomicOr(a.err, bad);
     for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = acc[k];
@@ -366,8 +375,7 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
         for (int k = 0; k < 9; ++k) G[k] = red[3 + k][0];
         // the origin p + R t_m also moves with R
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * (double)tm[j];
-        const double qd[4] = {q[0], q[1], q[2], q[3]};
+            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * tm[j];
         const double inv = 1.0 / sqrt(qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
         const double qn[4] = {qd[0] * inv, qd[1] * inv, qd[2] * inv, qd[3] * inv};
         double lqn[4], lq[4];

@@ -134,3 +134,52 @@ def test_directional_derivative_flags_silhouette_jumps():
     # with the jumped pixel removed, the rest of the image is a wall/backdrop seen head-on while the
     # camera moves sideways: depth is unchanged, so the corrected derivative vanishes
     assert abs(corr) < 1e-6
+
+
+def _split_wall(x, y0):
+    """A wall x = const made of two large triangles that share the vertical edge y = y0 (the other edges
+    far outside a 90-degree view from near the origin)."""
+    verts = np.array([[x, y0, -1000.0], [x, y0, 1000.0], [x, 2000.0, 0.0], [x, -2000.0, 0.0]])
+    return {"verts": verts, "tris": np.array([[0, 1, 2], [0, 1, 3]]), "rgb": np.array([[200, 0, 0], [0, 200, 0]],
+                                                                                      dtype=np.uint8)}
+
+
+def test_edge_mask_flags_the_column_on_a_shared_edge():
+    """Column 40's rays meet the wall at y = -5 u_40 exactly on the edge the two triangles share: that column
+    is flagged in every row and step, no other pixel is (the next columns are 5/32 m away), and the
+    columns either side hit different triangles."""
+    p = default_params(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0))
+    view = {"H": 4, "W": 64, "hfov": math.radians(90), "near": 0.01, "far": 100.0}
+    u40 = 2 * (40 + 0.5) / 64 - 1
+    sc = _split_wall(5.0, -5.0 * u40)
+    s0 = make_states([[0.0, 0.0, 5.0]], p, rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    acts = np.zeros((2, 1, 4))                       # free fall: the camera keeps y = 0 and its attitude
+    m = grd.rollout_edge_mask(s0, acts, p, sc, view, eps_edge=1e-4)
+    assert m.shape == (2, 1, 4 * 64)
+    expect = np.zeros((4, 64), dtype=bool)
+    expect[:, 40] = True
+    for k in range(2):
+        assert np.array_equal(m[k, 0].reshape(4, 64), expect)
+    ids = ren.render_view(dyn.rollout(s0, acts, p)[1, 0], sc, 4, 64, view["hfov"], with_mask=False)["id"]
+    assert set(ids[:, 39]) != set(ids[:, 41])
+
+
+def test_directional_derivative_removes_listed_pixel_steps():
+    """Removing every pixel-step leaves the goal term alone: moving toward the wall changes every depth,
+    yet the corrected derivative equals the goal term's closed form, sum_k 2 w (p_k - g) . u."""
+    p = default_params(ctrl=dyn.SRT, k_lin=(0.0, 0.0, 0.0))
+    view = {"H": 4, "W": 8, "hfov": math.radians(90), "near": 0.01, "far": 100.0}
+    sc = _split_wall(5.0, 0.3)
+    s0 = make_states([[0.0, 0.0, 5.0]], p, rotor=[[0, 0, 0, 0]]).astype(np.float64)
+    acts = np.zeros((3, 1, 4))
+    goal = np.array([[3.0, 1.0, 4.0]])
+    u_s = np.zeros_like(s0)
+    u_s[0, 0] = 1.0
+    everything = np.ones((3, 1, 32), dtype=bool)
+    d, smooth, corr, nj = grd.rollout_directional(s0, acts, p, sc, goal, view, u_s, np.zeros_like(acts),
+                                                  remove=everything)
+    traj = dyn.rollout(s0, acts, p)
+    goal_only = sum(2 * 0.01 * (traj[k, 0, 0:3] - goal[0]) @ u_s[0, 0:3] for k in range(1, 4))
+    assert nj == 96 and not smooth
+    assert abs(d - goal_only) > 1e-3                  # the depth terms do change
+    assert math.isclose(corr, goal_only, rel_tol=1e-6)
