@@ -82,7 +82,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 5}))
 
 
-TRAFFIC_SOURCES = ("render.hip", "vf_internal.h", "dynamics.h", "bvh_build.hip")
+TRAFFIC_SOURCES = ("render.hip", "vf_internal.h", "dynamics.h", "noise.h", "swarm.h", "bvh_build.hip")
 
 
 def traffic_source_hash():
