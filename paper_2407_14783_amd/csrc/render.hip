@@ -93,7 +93,7 @@ __device__ __forceinline__ void slab(float lo, float hi, float inv, float oi, fl
 
 // FIX: bit a set = every ray of the packet has the direction sign of bit a of SGN on axis a (set =
 // negative).  FIX = 7: one octant, all slab planes known at compile time; FIX = 0: the general test.
-template <int NR, bool STATS, int FIX, int SGN>
+template <int NR, bool STATS, int FIX, int SGN, bool DEEP>
 __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&valid)[NR], const float o[3],
                                              const float (&d)[NR][3], float t_near, float t_far,
                                              float (&t_best)[NR], int32_t (&id_best)[NR], uint32_t* err,
@@ -140,6 +140,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
     }
     if (__ballot(any) == 0ull) return;
 
+    // the stack: entry i in lane i of stk0, and for deep BVHs lane i - 64 of stk1
     int stk0 = 0, stk1 = 0;
     int sp = 0;
     int32_t entry = 0;          // root: inner node 0
@@ -238,16 +239,19 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                         const int32_t e67 = (int32_t)((k & 1u) ? w[kChildWord + 7] : w[kChildWord + 6]);
                         e = (k & 4u) ? ((k & 2u) ? e67 : e45) : e;
                     }
-                    // write lane sp of the two stack registers (lane compares + selects, no branch);
-                    // the depth limit of the build bounds sp below kStackCap
+                    // write lane sp of the stack registers (lane compares + selects, no branch); the
+                    // depth limit of the build bounds sp below kStackCap, and the launch takes the
+                    // one-register form only when every resident BVH is at most kShallowDepth deep
                     stk0 = lane_id() == sp ? e : stk0;
-                    stk1 = lane_id() == sp - 64 ? e : stk1;
+                    if constexpr (DEEP) stk1 = lane_id() == sp - 64 ? e : stk1;
                     if (STATS) {
                         const uint64_t cm = child_m[k];
                         mlo0 = lane_id() == sp ? (uint32_t)cm : mlo0;
                         mhi0 = lane_id() == sp ? (uint32_t)(cm >> 32) : mhi0;
-                        mlo1 = lane_id() == sp - 64 ? (uint32_t)cm : mlo1;
-                        mhi1 = lane_id() == sp - 64 ? (uint32_t)(cm >> 32) : mhi1;
+                        if constexpr (DEEP) {
+                            mlo1 = lane_id() == sp - 64 ? (uint32_t)cm : mlo1;
+                            mhi1 = lane_id() == sp - 64 ? (uint32_t)(cm >> 32) : mhi1;
+                        }
                     }
                     ++sp;
                 }
@@ -317,7 +321,7 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
         }
         if (sp == 0) break;
         --sp;
-        {
+        if constexpr (DEEP) {
             const int32_t a0 = __builtin_amdgcn_readlane(stk0, sp & 63);
             const int32_t a1 = __builtin_amdgcn_readlane(stk1, sp & 63);
             entry = sp < 64 ? a0 : a1;
@@ -325,6 +329,12 @@ __device__ __forceinline__ void trace_packet(const SceneDesc& sc, const bool (&v
                 const uint32_t l0 = __builtin_amdgcn_readlane(mlo0, sp & 63), h0 = __builtin_amdgcn_readlane(mhi0, sp & 63);
                 const uint32_t l1 = __builtin_amdgcn_readlane(mlo1, sp & 63), h1 = __builtin_amdgcn_readlane(mhi1, sp & 63);
                 act = sp < 64 ? ((uint64_t)h0 << 32 | l0) : ((uint64_t)h1 << 32 | l1);
+            }
+        } else {
+            entry = __builtin_amdgcn_readlane(stk0, sp);
+            if (STATS) {
+                const uint32_t l0 = __builtin_amdgcn_readlane(mlo0, sp), h0 = __builtin_amdgcn_readlane(mhi0, sp);
+                act = (uint64_t)h0 << 32 | l0;
             }
         }
     }
@@ -348,7 +358,7 @@ __device__ __forceinline__ bool view_ok(const RenderArgs& a, const vf_view& vw) 
     return true;
 }
 
-template <bool FUSED, bool STATS, bool NOISE, bool SWARM>
+template <bool FUSED, bool STATS, bool NOISE, bool SWARM, bool DEEP>
 __device__ __forceinline__ void render_body(const RenderArgs& a) {
     __shared__ float pose[17];
     __shared__ int ok_shared;
@@ -440,7 +450,7 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     if (!VF_OCTANT_PACKETS) fix = 0;
     if (!VF_PARTIAL_OCTANT && fix != 7) fix = 0;
     if (__builtin_popcount(fix) < 2) fix = 0;       // two or three mixed axes: the general test
-#define VF_TRACE(F, S) trace_packet<NR, STATS, F, S>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts, work)
+#define VF_TRACE(F, S) trace_packet<NR, STATS, F, S, DEEP>(sc, valid, o, d, vw.near_clip, vw.far_clip, t_best, id_best, a.err, ts, work)
     switch (fix == 0 ? 0 : (fix << 3) | sgn) {
         case (7 << 3) | 0: VF_TRACE(7, 0); break;
         case (7 << 3) | 1: VF_TRACE(7, 1); break;
@@ -540,11 +550,12 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
 }
 
 // The render kernel of split launches: occupancy of kRenderWavesPerEu waves per SIMD for the traversal.
-// SWARM: the views may show swarm members (the tree walk is compiled in).
-template <bool STATS, bool NOISE, bool SWARM>
+// SWARM: the views may show swarm members (the tree walk is compiled in).  DEEP: a resident BVH is deeper
+// than kShallowDepth, so the traversal stack takes two registers.
+template <bool STATS, bool NOISE, bool SWARM, bool DEEP>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kRenderWavesPerEu)))
 k_render(RenderArgs a) {
-    render_body<false, STATS, NOISE, SWARM>(a);
+    render_body<false, STATS, NOISE, SWARM, DEEP>(a);
 }
 
 // The fused kernel (small batches: few workgroups, so occupancy matters less than keeping the one-lane
@@ -552,7 +563,7 @@ k_render(RenderArgs a) {
 template <bool STATS, bool NOISE>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerEu)))
 k_render_fused(RenderArgs a) {
-    render_body<true, STATS, NOISE, false>(a);   // swarms always take split launches
+    render_body<true, STATS, NOISE, false, true>(a);   // swarms always take split launches
 }
 
 __global__ void __launch_bounds__(256) k_step(StepArgs a) {
@@ -777,16 +788,31 @@ static void launch_render_noise(bool noise, dim3 grid, dim3 block, hipStream_t s
             hipLaunchKernelGGL((k_render_fused<STATS, true>), grid, block, 0, st, a);
         else
             hipLaunchKernelGGL((k_render_fused<STATS, false>), grid, block, 0, st, a);
-    } else if (swarm) {
-        if (noise)
-            hipLaunchKernelGGL((k_render<STATS, true, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_render<STATS, false, true>), grid, block, 0, st, a);
+    } else if (STATS || a.max_depth > kShallowDepth) {
+        // the counting variants always take the two-register stack (they count the same walk)
+        if (swarm) {
+            if (noise)
+                hipLaunchKernelGGL((k_render<STATS, true, true, true>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_render<STATS, false, true, true>), grid, block, 0, st, a);
+        } else {
+            if (noise)
+                hipLaunchKernelGGL((k_render<STATS, true, false, true>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_render<STATS, false, false, true>), grid, block, 0, st, a);
+        }
     } else {
-        if (noise)
-            hipLaunchKernelGGL((k_render<STATS, true, false>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_render<STATS, false, false>), grid, block, 0, st, a);
+        if (swarm) {
+            if (noise)
+                hipLaunchKernelGGL((k_render<false, true, true, false>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_render<false, false, true, false>), grid, block, 0, st, a);
+        } else {
+            if (noise)
+                hipLaunchKernelGGL((k_render<false, true, false, false>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_render<false, false, false, false>), grid, block, 0, st, a);
+        }
     }
 }
 

@@ -165,13 +165,18 @@ static vf_status sync_scene_table(vf_ctx* ctx) {
     std::vector<SceneDesc> tab(kMaxScenes);
     std::vector<const int32_t*> lab(kMaxScenes, nullptr);
     memset(tab.data(), 0, sizeof(SceneDesc) * kMaxScenes);
+    int32_t deepest = 0;
     for (size_t i = 0; i < ctx->scenes.size(); ++i)
         if (ctx->scenes[i].used) {
+            deepest = std::max(deepest, (int32_t)ctx->scenes[i].info.depth);
             tab[i] = ctx->scenes[i].desc;
             lab[i] = ctx->scenes[i].labels;
         }
+    // a deeper scene is announced before the device table holds it, a shallower maximum only after
+    if (deepest > ctx->max_bvh_depth.load()) ctx->max_bvh_depth.store(deepest);
     VF_HIP(hipMemcpy(ctx->d_scenes, tab.data(), sizeof(SceneDesc) * kMaxScenes, hipMemcpyHostToDevice));
     VF_HIP(hipMemcpy(ctx->d_labels, lab.data(), sizeof(void*) * kMaxScenes, hipMemcpyHostToDevice));
+    ctx->max_bvh_depth.store(deepest);
     return VF_OK;
 }
 
@@ -497,6 +502,7 @@ static RenderArgs make_render_args(vf_ctx* ctx, int64_t n, const int32_t* env_id
     a.stats = ctx->d_stats;
     a.swarm = ctx->swarm;
     a.noise = ctx->render_noise;
+    a.max_depth = ctx->max_bvh_depth.load();
     return a;
 }
 

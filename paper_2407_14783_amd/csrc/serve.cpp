@@ -221,6 +221,7 @@ struct HipBackend {
         ra.out_pixels = px;
         ra.err = d_err;
         ra.stats = s->ctx->d_stats;
+        ra.max_depth = s->ctx->max_bvh_depth.load();
         // no swarms (server views show none) and no spatial order: for the server's batches (mostly one or two
         // requests) the ordering kernel cost more than the cache locality it bought
         if (e == hipSuccess) e = launch_render(ra, false, false, false, a.stream);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <list>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <string>
@@ -63,6 +64,10 @@ constexpr int kStackCap = 128;        // traversal stack entries per wavefront (
 constexpr int kMaxBvhDepth = kWidth == 4 ? 40 : 18;
 // a packet keeps at most kWidth - 1 pending siblings per level of its path plus the children just pushed
 static_assert((kWidth - 1) * (kMaxBvhDepth - 1) + kWidth <= kStackCap, "traversal stack cannot overflow");
+// BVHs up to this depth keep a packet's pending entries within one VGPR's 64 lanes: launches over such
+// scenes only take the render with a one-register stack
+constexpr int kShallowDepth = (kWave - kWidth) / (kWidth - 1) + 1;
+static_assert((kWidth - 1) * (kShallowDepth - 1) + kWidth <= kWave, "one stack register holds a shallow BVH's walk");
 constexpr int kMaxScenes = 1024;
 constexpr int kServerMaxAttempts = 8;   // batches a server request may be launched in before it fails
 constexpr int kMaxImage = 1024;
@@ -259,6 +264,7 @@ struct vf_ctx {
     int64_t used = 0;
     std::mutex mu;
     std::vector<vf::SceneHost> scenes;
+    std::atomic<int32_t> max_bvh_depth{0};  // deepest BVH of the resident scenes
     vf::SceneDesc* d_scenes = nullptr;     // device scene table [kMaxScenes]
     const int32_t** d_labels = nullptr;    // device table of per-scene label arrays [kMaxScenes]
     uint32_t* d_err = nullptr;             // sticky error word of the calls that take a stream
@@ -316,6 +322,7 @@ struct RenderArgs {
     SwarmTable swarm;
     DynConstD dyn;
     vf_noise noise;               // depth / colour noise of the epilogue (read by the noise variant only)
+    int32_t max_depth;            // deepest BVH of the resident scenes (picks the stack form, host only)
 };
 struct OrderArgs {
     int32_t n;

@@ -683,6 +683,78 @@ def test_duplicate_geometry_builds_balanced(vf):
     ctx.free_scene(sid)
 
 
+def _chain_scene(n, ratio=2.2, half=0.5, seed=12):
+    """n equal triangles facing a camera at the origin, centred on its axis at x = ratio^k.  For ratio > 2
+    the cheapest merge of triangle k is with the cluster of all nearer ones, and of that cluster with k,
+    so the clustering merges one pair per pass: a chain, as deep as a BVH of n leaves can be.  A ray
+    along the axis enters every box of it."""
+    verts, tris = [], []
+    for k in range(n):
+        x = ratio ** k
+        verts += [(x, -half, -half), (x, half, -half), (x, 0.0, half)]
+        tris.append((3 * k, 3 * k + 1, 3 * k + 2))
+    rgb = np.random.default_rng(seed).integers(0, 256, (n, 3))
+    return {"verts": np.asarray(verts, dtype=np.float32), "tris": np.asarray(tris, dtype=np.int32),
+            "rgb": rgb.astype(np.uint8)}
+
+
+SHALLOW_DEPTH = 21    # deepest 4-wide BVH whose walk fits one 64-lane stack register: 3 (d - 1) + 4 <= 64
+
+
+def test_deep_bvh_takes_the_two_register_stack(vf):
+    """A BVH deeper than one stack register holds is rendered right (against the oracle), and while it is
+    resident every launch takes the two-register stack: another scene renders to the same bits as with
+    only shallow scenes resident, before and after the deep scene is freed."""
+    sim, ctx = vf
+    p = default_params()
+    room = scenes.box_room(seed=1)
+    sid_room = ctx.build_scene(room["verts"], room["tris"], room["rgb"])
+    rng = np.random.default_rng(21)
+    q = rng.normal(size=(6, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    poses = agents.make_states(rng.uniform([2, 2, 1], [8, 8, 3], (6, 3)), p, quat=q)
+    shallow = _render(ctx, sim, sid_room, poses)
+    ctx.set_bvh_leaf_size(1)
+    sid = None
+    try:
+        for n in (75, 90, 105):
+            sc = _chain_scene(n)
+            sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+            depth_n = ctx.scene_info(sid)["depth"]
+            if depth_n > SHALLOW_DEPTH:
+                break
+            ctx.free_scene(sid)
+            sid = None
+        header(f"deep BVH: {n} chained triangles, depth {depth_n}")
+        assert sid is not None, f"no chain scene built deeper than {SHALLOW_DEPTH} levels (last: {depth_n})"
+        # the far plane beyond the chain's last triangle, so the packet walks the whole chain
+        far = 1e30
+        cam = agents.make_states([[0.0, 0.0, 0.0]], p)
+        views, npx, offs, mh, mw = sim.make_views(1, sid, (48, 48), far=far)
+        depth_t = torch.full((npx,), -7.0, dtype=torch.float32).cuda()
+        ids_t = torch.full((npx,), -9, dtype=torch.int32).cuda()
+        ctx.render(_dev(cam), views, max_hw=(mh, mw), depth=depth_t, tri_id=ids_t, out_pixels=npx)
+        ctx.sync_check()
+        ref = oren.render_view(cam[0].astype(np.float64), sc, 48, 48, math.pi / 2, far=far)
+        ids = ids_t.cpu().numpy()
+        assert (ids >= 0).sum() > 200
+        compare_render(depth_t.cpu().numpy(), ids, None, ref, far, "deep chain")
+        deep = _render(ctx, sim, sid_room, poses)
+        for a, b in zip(shallow[:3], deep[:3]):
+            assert np.array_equal(a, b), "the two stack forms give different images"
+        ctx.free_scene(sid)
+        sid = None
+        after = _render(ctx, sim, sid_room, poses)
+        for a, b in zip(shallow[:3], after[:3]):
+            assert np.array_equal(a, b)
+        record("deep_bvh", depth=int(depth_n), triangles=int(n))
+    finally:
+        if sid is not None:
+            ctx.free_scene(sid)
+        ctx.set_bvh_leaf_size(4)
+        ctx.free_scene(sid_room)
+
+
 def _look_quat(f):
     """Attitude whose body x axis (the camera axis) points along f, with no roll."""
     f = np.asarray(f, dtype=np.float64) / np.linalg.norm(f)
