@@ -238,7 +238,10 @@ vf_status vf_render(vf_ctx* ctx, int64_t n, const int32_t* env_idx, const float*
  * (ds_{k+1}/da_k)^T grad_state_out [n][4] (both overwritten).  The forward
  * sub-steps are recomputed from state_in.  Clamped rotor commands pass no
  * gradient; the square root of a zero rotor command passes none either.
- * Covers ctrl VF_CTBR and VF_SRT; VF_PS / VF_LV return VF_EINVAL. */
+ * Every controller: VF_CTBR and VF_SRT by a hand-written reverse mode, VF_PS
+ * and VF_LV by forward mode (one dual-number pass per input coordinate, 21
+ * per agent), where the outer loop's lift and tilt limits pass the gradient
+ * of the side the forward took. */
 vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const float* state_in,
                            const float* action, const float* grad_state_out, float* grad_state_in,
                            float* grad_action, void* stream);

@@ -17,7 +17,8 @@
 // note.  Every expression is evaluated as written (no multiply-add contraction), so
 // every kernel that steps agents -- the dynamics kernel, the fused render, the
 // server's batches -- computes the same bits.  The adjoint (grad.hip) recomputes the
-// same FP64 sub-steps and linearises them in FP64 too.
+// same FP64 sub-steps and linearises them in FP64 too: in reverse mode by hand for
+// CTBR and SRT, and for PS and LV by running dyn_substep itself on dual numbers.
 #pragma once
 
 #include "vf_internal.h"
@@ -203,41 +204,43 @@ __device__ __forceinline__ void axpy13(Vec13T<T>& o, const Vec13T<T>& y, T h, co
     for (int i = 0; i < 3; ++i) o.w[i] = y.w[i] + h * k.w[i];
 }
 
-// One sub-step of length c.h in FP64: s (17) and the held action a (4) -> s, in place.
-__device__ __forceinline__ void dyn_substep(const DynConstD& c, double s[17], const double a[4]) {
+// One sub-step of length c.h: s (17) and the held action a (4) -> s, in place.  The control step runs it in
+// FP64; the forward-mode adjoint runs it on dual numbers, whose values take the same operations.
+template <typename T>
+__device__ __forceinline__ void dyn_substep(const DynConstT<T>& c, T s[17], const T a[4]) {
 #pragma clang fp contract(off)
-    double fdes[4], wd[4], w0[4], wh[4], wf[4];
+    T fdes[4], wd[4], w0[4], wh[4], wf[4];
     controller(c, s, a, fdes);
     for (int i = 0; i < 4; ++i) {
-        wd[i] = sqrt(fdes[i]);
+        wd[i] = vsqrt(fdes[i]);
         w0[i] = s[13 + i];
         wh[i] = wd[i] + (w0[i] - wd[i]) * c.e_half;
         wf[i] = wd[i] + (w0[i] - wd[i]) * c.e_full;
     }
-    Vec13T<double> y;
+    Vec13T<T> y;
     for (int i = 0; i < 3; ++i) { y.p[i] = s[i]; y.v[i] = s[7 + i]; y.w[i] = s[10 + i]; }
     for (int i = 0; i < 4; ++i) y.q[i] = s[3 + i];
-    Vec13T<double> k1, k2, k3, k4, t;
-    const double h = c.h;
+    Vec13T<T> k1, k2, k3, k4, t;
+    const T h = c.h;
     derivative(c, y, w0, k1);
     if (c.integrator == VF_EULER) {
         axpy13(y, y, h, k1);
     } else {
-        axpy13(t, y, 0.5 * h, k1);
+        axpy13(t, y, T(0.5) * h, k1);
         derivative(c, t, wh, k2);
-        axpy13(t, y, 0.5 * h, k2);
+        axpy13(t, y, T(0.5) * h, k2);
         derivative(c, t, wh, k3);
         axpy13(t, y, h, k3);
         derivative(c, t, wf, k4);
-        const double h6 = h / 6.0;
+        const T h6 = h / T(6);
         for (int i = 0; i < 3; ++i) {
-            y.p[i] += h6 * (k1.p[i] + 2.0 * (k2.p[i] + k3.p[i]) + k4.p[i]);
-            y.v[i] += h6 * (k1.v[i] + 2.0 * (k2.v[i] + k3.v[i]) + k4.v[i]);
-            y.w[i] += h6 * (k1.w[i] + 2.0 * (k2.w[i] + k3.w[i]) + k4.w[i]);
+            y.p[i] += h6 * (k1.p[i] + T(2) * (k2.p[i] + k3.p[i]) + k4.p[i]);
+            y.v[i] += h6 * (k1.v[i] + T(2) * (k2.v[i] + k3.v[i]) + k4.v[i]);
+            y.w[i] += h6 * (k1.w[i] + T(2) * (k2.w[i] + k3.w[i]) + k4.w[i]);
         }
-        for (int i = 0; i < 4; ++i) y.q[i] += h6 * (k1.q[i] + 2.0 * (k2.q[i] + k3.q[i]) + k4.q[i]);
+        for (int i = 0; i < 4; ++i) y.q[i] += h6 * (k1.q[i] + T(2) * (k2.q[i] + k3.q[i]) + k4.q[i]);
     }
-    const double inv = 1.0 / sqrt(y.q[0] * y.q[0] + y.q[1] * y.q[1] + y.q[2] * y.q[2] + y.q[3] * y.q[3]);
+    const T inv = T(1) / vsqrt(y.q[0] * y.q[0] + y.q[1] * y.q[1] + y.q[2] * y.q[2] + y.q[3] * y.q[3]);
     for (int i = 0; i < 3; ++i) { s[i] = y.p[i]; s[7 + i] = y.v[i]; s[10 + i] = y.w[i]; }
     for (int i = 0; i < 4; ++i) { s[3 + i] = y.q[i] * inv; s[13 + i] = wf[i]; }
 }

@@ -10,6 +10,10 @@
 // rotor lag (Eq. 4), the square root, the clamp (zero gradient when clamped)
 // and the CTBR mixer / rate controller.
 //
+// k_step_backward_tangent: the same step's Jacobian-transpose product by forward mode (dual numbers
+// through the templated FP64 sub-steps), one thread per agent and input coordinate; used for the PS and LV
+// controllers.
+//
 // k_render_backward (in FP64): depth t = n.(V0 - o) / n.d on the hit triangle's plane;
 // dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B with d_B = R_m d_cam and
 // o = p + R t_m for a camera mounted at (R_m, t_m).  Per agent the pixel
@@ -295,6 +299,111 @@ __global__ void __launch_bounds__(128) k_step_backward(StepBackArgs a) {
     for (int k = 0; k < 4; ++k) a.grad_action[(int64_t)i * 4 + k] = (float)la[k];
 }
 
+// ---------------------------------------------------------------------------
+// Forward-mode form of the step adjoint (every controller; the launcher takes it for PS and LV, whose
+// outer loop has no hand-written reverse): dual numbers v + d eps carry one tangent through the same
+// templated sub-steps.  Each value is the FP64 operation the control step performs (contraction off, as
+// there), so the tangent is the derivative of exactly the computation the forward runs.  Branches (the
+// tilt limit) and clamps take the derivative of the side the value took.
+// ---------------------------------------------------------------------------
+struct Dual {
+    double v, d;
+    __device__ Dual() : v(0.0), d(0.0) {}
+    __device__ Dual(double x) : v(x), d(0.0) {}
+    __device__ Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) {
+#pragma clang fp contract(off)
+    return Dual(a.v + b.v, a.d + b.d);
+}
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) {
+#pragma clang fp contract(off)
+    return Dual(a.v - b.v, a.d - b.d);
+}
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) {
+#pragma clang fp contract(off)
+    return Dual(a.v * b.v, a.d * b.v + a.v * b.d);
+}
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+#pragma clang fp contract(off)
+    const double q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+__device__ __forceinline__ Dual& operator*=(Dual& a, Dual b) { return a = a * b; }
+__device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ __forceinline__ Dual vsqrt(Dual x) {
+    const double r = sqrt(x.v);
+    // a clamped zero (tangent 0) stays flat instead of 0 / 0
+    return Dual(r, x.d == 0.0 ? 0.0 : x.d / (2.0 * r));
+}
+__device__ __forceinline__ Dual vabs(Dual x) { return x.v < 0.0 ? -x : x; }
+// the operand fmin / fmax return (the non-NaN one, the first at a tie) with its tangent
+__device__ __forceinline__ Dual vmin(Dual a, Dual b) { return fmin(a.v, b.v) == a.v ? a : b; }
+__device__ __forceinline__ Dual vmax(Dual a, Dual b) { return fmax(a.v, b.v) == a.v ? a : b; }
+__device__ __forceinline__ void vsincos(Dual x, Dual* s, Dual* c) {
+    double sv, cv;
+    sincos(x.v, &sv, &cv);
+    *s = Dual(sv, cv * x.d);
+    *c = Dual(cv, -sv * x.d);
+}
+
+__device__ __forceinline__ DynConstT<Dual> dual_const(const DynConstD& c) {
+    DynConstT<Dual> o;
+    o.h = c.h;
+    o.n_sub = c.n_sub;
+    o.integrator = c.integrator;
+    o.ctrl = c.ctrl;
+    o.mass = c.mass;
+    o.inv_mass = c.inv_mass;
+    o.g = c.g;
+    for (int i = 0; i < 3; ++i) {
+        o.J[i] = c.J[i];
+        o.inv_J[i] = c.inv_J[i];
+        o.kJ[i] = c.kJ[i];
+        o.k_lin[i] = c.k_lin[i];
+        o.c_quad[i] = c.c_quad[i];
+        o.k_pos[i] = c.k_pos[i];
+        o.k_vel[i] = c.k_vel[i];
+        o.k_att[i] = c.k_att[i];
+    }
+    o.arm_a = c.arm_a;
+    o.inv_a = c.inv_a;
+    o.kappa = c.kappa;
+    o.inv_kappa = c.inv_kappa;
+    o.f_max = c.f_max;
+    o.e_half = c.e_half;
+    o.e_full = c.e_full;
+    o.tan_tilt = c.tan_tilt;
+    o.min_lift = c.min_lift;
+    return o;
+}
+
+// One thread per (agent, input coordinate j of the 17 state and 4 action values): the control step on
+// dual numbers seeded with e_j gives column j of the step Jacobian, and its dot product with the output
+// cotangent is component j of the input cotangent.  The n_sub sub-steps run once each.
+constexpr int kTangentThreads = 64;
+__global__ void __launch_bounds__(kTangentThreads) k_step_backward_tangent(StepBackArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)a.n * 21) return;
+    const int64_t i = t / 21;
+    const int j = (int)(t - i * 21);
+    const DynConstT<Dual> c = dual_const(a.dyn);
+    Dual s[17], act[4];
+    for (int k = 0; k < 17; ++k) s[k] = Dual((double)a.state_in[i * 17 + k], k == j ? 1.0 : 0.0);
+    for (int k = 0; k < 4; ++k) act[k] = Dual((double)a.action[i * 4 + k], 17 + k == j ? 1.0 : 0.0);
+    for (int sub = 0; sub < a.dyn.n_sub; ++sub) dyn_substep(c, s, act);
+    double g = 0.0;
+    for (int k = 0; k < 17; ++k) g += (double)a.grad_out[i * 17 + k] * s[k].d;
+    if (j < 17)
+        a.grad_in[i * 17 + j] = (float)g;
+    else
+        a.grad_action[i * 4 + (j - 17)] = (float)g;
+}
+
 constexpr int kBackThreads = 256;
 
 __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs a) {
@@ -387,7 +496,13 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
 
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_step_backward, dim3((a.n + 127) / 128), dim3(128), 0, st, a);
+    if (a.dyn.ctrl == VF_PS || a.dyn.ctrl == VF_LV) {
+        const int64_t threads = (int64_t)a.n * 21;
+        hipLaunchKernelGGL(k_step_backward_tangent, dim3((unsigned)((threads + kTangentThreads - 1) / kTangentThreads)),
+                           dim3(kTangentThreads), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_step_backward, dim3((a.n + 127) / 128), dim3(128), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -643,8 +643,6 @@ vf_status vf_step_backward(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, 
         return fail(VF_EINVAL, "vf_step_backward: NULL array");
     std::string why;
     if (!check_dyn_params(*params, &why)) return fail(VF_EINVAL, "vf_step_backward: " + why);
-    if (params->ctrl != VF_CTBR && params->ctrl != VF_SRT)
-        return fail(VF_EINVAL, "vf_step_backward: the adjoint covers the CTBR and SRT controllers");
     if (n == 0) return VF_OK;
     VF_HIP(hipSetDevice(ctx->device));
     StepBackArgs a{(int32_t)n, state_in, action, grad_state_out, grad_state_in, grad_action,

@@ -51,13 +51,22 @@ def _random_states(rng, n, p, rate=1.0, speed=1.5):
 
 
 @pytest.mark.parametrize("variant", ["ctbr", "ctbr_saturating", "srt", "euler_nsub2", "rk4_nsub3", "quad_drag",
-                                     "quad_drag_srt"])
+                                     "quad_drag_srt", "ps", "lv", "ps_euler_nsub2_drag"])
 def test_step_backward_matches_fd_jacobian(vf, variant):
+    """J_s^T lam and J_a^T lam of one control step against the oracle's central-difference Jacobians.  CTBR
+    and SRT take the hand-written reverse-mode kernel, PS and LV the forward-mode (dual number) one."""
     sim, ctx = vf
     rng = np.random.default_rng({"ctbr": 1, "ctbr_saturating": 2, "srt": 3, "euler_nsub2": 4, "rk4_nsub3": 5,
-                                 "quad_drag": 6, "quad_drag_srt": 7}[variant])
+                                 "quad_drag": 6, "quad_drag_srt": 7, "ps": 8, "lv": 9,
+                                 "ps_euler_nsub2_drag": 10}[variant])
     speed = 1.5
-    if variant == "quad_drag":
+    if variant == "ps":
+        p = default_params(ctrl=odyn.PS)
+    elif variant == "lv":
+        p = default_params(ctrl=odyn.LV)
+    elif variant == "ps_euler_nsub2_drag":
+        p = default_params(ctrl=odyn.PS, integrator=odyn.EULER, n_sub=2, c_quad=(0.04, 0.06, 0.1))
+    elif variant == "quad_drag":
         # Eq. 2 with both terms, at body speeds (about 7 m/s) where the quadratic term dominates
         p = default_params(c_quad=(0.04, 0.06, 0.1))
         speed = 4.0
@@ -78,6 +87,12 @@ def test_step_backward_matches_fd_jacobian(vf, variant):
         a = (p["mass"] * p["g"] / 4 * rng.uniform(0.7, 1.3, (n, 4))).astype(np.float32)
     elif variant == "ctbr_saturating":
         a = agents.random_actions(int(rng.integers(1 << 30)), 1, n, p)[0]
+    elif variant.startswith("ps"):
+        # position setpoints within 3 m of the agent and a yaw setpoint
+        a = np.concatenate([s[:, 0:3] + rng.uniform(-3, 3, (n, 3)), rng.uniform(-np.pi, np.pi, (n, 1))], 1).astype(
+            np.float32)
+    elif variant == "lv":
+        a = np.concatenate([rng.uniform(-2, 2, (n, 3)), rng.uniform(-np.pi, np.pi, (n, 1))], 1).astype(np.float32)
     else:
         a = np.concatenate([rng.uniform(0.8, 1.2, (n, 1)) * p["g"], rng.uniform(-0.5, 0.5, (n, 3))], 1).astype(
             np.float32)
@@ -227,6 +242,53 @@ def test_bptt_rollout_gradient_vs_oracle_fd(vf, w_goal):
         jumps.append(n_jumps)
     record(f"bptt_directions[w_goal={w_goal}]", compared=N_DIRECTIONS, of=N_DIRECTIONS, worst_rel=worst,
            bound=BPTT_TOL, jumped_pixel_steps=jumps)
+    ctx.free_scene(sid)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("ctrl", ["ps", "lv"])
+def test_bptt_outer_loop_controllers_vs_oracle_fd(vf, ctrl):
+    """The checkpointed BPTT through the PS and LV controllers (forward-mode step adjoint): 2 agents of the
+    differentiable configuration's forest, horizon 16, position (PS) or velocity (LV) setpoints; the
+    directional derivative along 4 seeded directions against the oracle's FP64 central differences,
+    within 1e-3 relative (jumped and edge pixel-steps removed from both sides, as above)."""
+    sim, ctx = vf
+    from paper_2407_14783_amd import autograd as vag
+    p0, _, s0_all, _, goals_all, _ = _bptt_setup()
+    p = default_params(ctrl=odyn.PS if ctrl == "ps" else odyn.LV)
+    n, H = 2, 16
+    s0, goals = s0_all[:n], goals_all[:n]
+    rng = np.random.default_rng({"ps": 41, "lv": 42}[ctrl])
+    if ctrl == "ps":
+        target = s0[:, 0:3] + rng.uniform(-2.0, 2.0, (n, 3))
+        acts = np.repeat(np.concatenate([target, rng.uniform(-1, 1, (n, 1))], 1)[None], H, 0)
+    else:
+        acts = np.repeat(np.concatenate([rng.uniform(-1.5, 1.5, (n, 3)), rng.uniform(-1, 1, (n, 1))], 1)[None], H, 0)
+    acts = (acts + rng.normal(scale=0.05, size=acts.shape)).astype(np.float32)
+    full = scenes.forest(seed=3)
+    sc = _crop_forest(full, s0[:, 0:3], 6.0)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    header(f"BPTT through {ctrl.upper()}: {n} agents x {H} steps, {sc['tris'].shape[0]} triangles")
+    pd = device_params(p)
+    traj_ok = odyn.rollout(s0.astype(np.float64), acts.astype(np.float64), pd)
+    assert np.isfinite(traj_ok).all()
+    edges = ograd.rollout_edge_mask(s0, acts, pd, sc, VIEW64, eps_edge=1e-4)
+    worst = 0.0
+    for j in range(4):
+        u_s = rng.normal(size=s0.shape)
+        u_a = rng.normal(size=acts.shape)
+        norm = math.sqrt((u_s ** 2).sum() + (u_a ** 2).sum())
+        u_s, u_a = u_s / norm, u_a / norm
+        _, _, fd_c, n_removed, removed = ograd.rollout_directional(s0, acts, pd, sc, goals, VIEW64, u_s, u_a, h=1e-6,
+                                                                    w_goal=0.01, return_jumps=True, remove=edges)
+        _, gs, ga = _gpu_gradient(ctx, sim, vag, p, sid, s0, acts, goals, 0.01, keep=~removed)
+        ad = float((gs * u_s).sum() + (ga * u_a).sum())
+        rel = abs(ad - fd_c) / max(abs(fd_c), 1e-3)
+        print(f"[gpu-test] {ctrl} direction {j}: adjoint {ad:.6e} fd {fd_c:.6e} rel {rel:.2e} "
+              f"({n_removed} pixel-steps removed)", flush=True)
+        assert rel <= BPTT_TOL, f"{ctrl} direction {j}: adjoint {ad} vs fd {fd_c} (rel {rel:.2e})"
+        worst = max(worst, rel)
+    record(f"bptt_outer_loop[{ctrl}]", directions=4, worst_rel=worst, bound=BPTT_TOL)
     ctx.free_scene(sid)
 
 
