@@ -7,10 +7,12 @@ end: it re-runs the segment's dynamics from the saved state checkpoint, then for
 each step in reverse adds the state-output gradient, accumulates the
 depth-to-pose adjoint (vf_render_backward) into the state cotangent and applies
 the RK4 step adjoint (vf_step_backward).  The depth adjoint needs each frame's
-hit ids: with ``keep_ids`` (the default) the forward keeps them, H x P int32
-(1 GiB for 1,024 agents x 64 steps of 64x64), and backward renders nothing;
-without, backward re-renders each segment to recover them (memory: one segment
-of ids).  State checkpoints take N x 17 floats each.
+hit ids, H x P int32 for the horizon (1 GiB for 1,024 agents x 64 steps of
+64x64).  ``keep_ids``: True keeps them from the forward and backward renders
+nothing; False keeps one segment's worth and backward re-renders each segment
+(about twice the rollout time); None (the default) keeps them while they fit
+``ids_budget_bytes`` (4 GiB) and re-renders beyond.  State checkpoints take
+N x 17 floats each.
 All arithmetic runs in the library's kernels; torch only holds the buffers.
 """
 import torch
@@ -78,8 +80,15 @@ class _Rollout(torch.autograd.Function):
         return lam.clone(), g_act, None, None, None, None, None, None, None
 
 
-def rollout(sim_ctx, params, s0, actions, views, max_hw, out_pixels, checkpoint_every=8, keep_ids=True):
+IDS_BUDGET_BYTES = 4 << 30
+
+
+def rollout(sim_ctx, params, s0, actions, views, max_hw, out_pixels, checkpoint_every=8, keep_ids=None,
+            ids_budget_bytes=IDS_BUDGET_BYTES):
     """States [H, N, 17] and depth images [H, out_pixels] of an H-step rollout, differentiable in s0 and actions.
-    keep_ids: keep every frame's hit ids for the backward pass (else re-render each segment there)."""
+    keep_ids: keep every frame's hit ids for the backward pass (True), re-render each segment there (False), or
+    keep them while H x out_pixels x 4 bytes fit ids_budget_bytes (None)."""
+    if keep_ids is None:
+        keep_ids = actions.shape[0] * int(out_pixels) * 4 <= ids_budget_bytes
     return _Rollout.apply(s0, actions, sim_ctx, params, views, tuple(max_hw), int(out_pixels),
                           int(checkpoint_every), bool(keep_ids))

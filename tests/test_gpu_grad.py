@@ -373,14 +373,17 @@ def test_bptt_kept_ids_equal_rerendered(vf):
     views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
     header("BPTT: kept hit ids vs re-rendered segments, 6 agents x 20 steps, k = 8")
     grads = []
-    for keep in (True, False):
+    # kept, re-rendered, and the default's choice under a budget too small for the ids (re-rendered)
+    for keep, budget in ((True, 0), (False, 0), (None, 1024)):
         s0_t = _dev(s0).requires_grad_(True)
         a_t = _dev(acts).requires_grad_(True)
-        states, depths = vag.rollout(ctx, p, s0_t, a_t, views, (mh, mw), npx, checkpoint_every=8, keep_ids=keep)
+        states, depths = vag.rollout(ctx, p, s0_t, a_t, views, (mh, mw), npx, checkpoint_every=8, keep_ids=keep,
+                                     ids_budget_bytes=budget)
         loss = torch.exp(-depths).view(H, n, -1).mean(2).sum() + 0.01 * (states[:, :, 0:3] ** 2).sum()
         loss.backward()
         grads.append((s0_t.grad.cpu().numpy(), a_t.grad.cpu().numpy(), loss.item()))
-    assert grads[0][2] == grads[1][2]
-    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    for other in grads[1:]:
+        assert grads[0][2] == other[2]
+        assert np.array_equal(grads[0][0], other[0]) and np.array_equal(grads[0][1], other[1])
     assert np.abs(grads[0][1]).max() > 0
     ctx.free_scene(sid)
