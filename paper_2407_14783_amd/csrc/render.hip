@@ -1,6 +1,6 @@
 // Batched step + ray-cast render kernels (Sec. III-A dynamics, Sec. III-B views).
 //
-// One wavefront traces one 8 x 8 pixel packet of one agent.  The packet walks
+// One wavefront traces one 16 x 4 pixel packet (kTileH x kTileW) of one agent.  The packet walks
 // the 4-wide BVH together: every node and leaf triangle is fetched once per
 // wavefront through the scalar data path (wave-uniform address), each lane
 // tests its own ray, and ballots decide which children the packet visits.  The
@@ -402,9 +402,9 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     const SceneDesc sc = a.scenes[vw.scene_id];
 
 
-    // the wavefront's packet: kPacketRows x kPacketCols 8x8 sub-tiles, one ray of each per lane
+    // the wavefront's packet: kPacketRows x kPacketCols tiles of kTileH x kTileW, one ray of each per lane
     constexpr int NR = kPacketRows * kPacketCols;
-    const int th = kTile * kPacketRows, tw_ = kTile * kPacketCols;
+    const int th = kTileH * kPacketRows, tw_ = kTileW * kPacketCols;
     const int tiles_x = (vw.W + tw_ - 1) / tw_;
     const int tiles_y = (vw.H + th - 1) / th;
     const int tile = group * kWavesPerBlock + wave;
@@ -414,8 +414,8 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     bool valid[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-        row[k] = ty * th + (k / kPacketCols) * kTile + (lane >> 3);
-        col[k] = tx * tw_ + (k % kPacketCols) * kTile + (lane & 7);
+        row[k] = ty * th + (k / kPacketCols) * kTileH + lane / kTileW;
+        col[k] = tx * tw_ + (k % kPacketCols) * kTileW + lane % kTileW;
         valid[k] = row[k] < vw.H && col[k] < vw.W;
     }
 
@@ -775,7 +775,7 @@ hipError_t launch_group_order(const GroupOrderArgs& a, hipStream_t st) {
 }
 
 int32_t render_groups_per_agent(int32_t max_h, int32_t max_w) {
-    const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
+    const int th = kTileH * kPacketRows, tw = kTileW * kPacketCols;
     int tiles = ((max_h + th - 1) / th) * ((max_w + tw - 1) / tw);
     return (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
 }

@@ -529,7 +529,7 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
                                     out_pixels);
     bool split = ctx->launch_mode == VF_LAUNCH_SPLIT;
     if (ctx->launch_mode == VF_LAUNCH_AUTO) {
-        const int th = kTile * kPacketRows, tw = kTile * kPacketCols;
+        const int th = kTileH * kPacketRows, tw = kTileW * kPacketCols;
         int64_t tiles = (int64_t)((max_h + th - 1) / th) * ((max_w + tw - 1) / tw);
         int64_t groups = n * ((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
         split = groups > 1024;

@@ -20,7 +20,14 @@ namespace vf {
 // launch geometry
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;             // CDNA wavefront
-constexpr int kTile = 8;              // 8 x 8 pixel packet per wavefront
+#ifndef VF_TILE_W
+#define VF_TILE_W 4
+#endif
+// a wavefront's packet: kTileH x kTileW pixels, one ray per lane.  Tall packets (16 x 4) keep the rays of a
+// vertical edge -- trunks, walls, pillars seen by a level camera -- in fewer packets than 8 x 8 squares
+constexpr int kTileW = VF_TILE_W;
+constexpr int kTileH = 64 / kTileW;
+static_assert(kTileW * kTileH == 64 && kTileW >= 1, "a packet has one ray per lane of a wavefront");
 #ifndef VF_OCTANT_PACKETS
 #define VF_OCTANT_PACKETS 1   // packets of one ray octant take the traversal with fixed slab planes
 #endif
@@ -43,7 +50,7 @@ constexpr int kCostBuckets = 32;
 #ifndef VF_PACKET_COLS
 #define VF_PACKET_COLS 1
 #endif
-constexpr int kPacketRows = VF_PACKET_ROWS;  // a wavefront's packet: rows x cols of 8x8 tiles,
+constexpr int kPacketRows = VF_PACKET_ROWS;  // a wavefront's packet: rows x cols of such tiles,
 constexpr int kPacketCols = VF_PACKET_COLS;  // one ray of each per lane
 #ifndef VF_LEAF_MAX
 #define VF_LEAF_MAX 4

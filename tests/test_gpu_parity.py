@@ -4,7 +4,7 @@ Dynamics: trajectories from the same float32 start states and actions, state
 within 1e-5 * max(1, |s|) per component after every one of 100 steps.
 Render: the oracle renders at the GPU's float32 poses (upcast); off the oracle's
 edge/tie mask the hit ids and colours are bit-exact and depth is within 1e-4
-relative.  Sizes span several 8x8 tiles, ragged image edges and many BVH levels.
+relative.  Sizes span several 16x4 packets, ragged image edges and many BVH levels.
 """
 import math
 
@@ -241,7 +241,7 @@ def test_render_forest_full_frames(vf):
 
 
 def test_render_ragged_sizes_and_fov(vf):
-    """Image sizes that are not multiples of the 8x8 tile, non-square, other fields of view."""
+    """Image sizes that are not multiples of the 16x4 packet, non-square, other fields of view."""
     sim, ctx = vf
     p = default_params()
     sc = scenes.box_room(seed=4)
