@@ -566,8 +566,8 @@ k_render_fused(RenderArgs a) {
     render_body<true, STATS, NOISE, false, true>(a);   // swarms always take split launches
 }
 
-__global__ void __launch_bounds__(256) k_step(StepArgs a) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Agent i's control step on its state slot.
+__device__ __forceinline__ void step_agent(const StepArgs& a, int i) {
     if (i >= a.n) return;
     int64_t slot = a.env_idx ? (int64_t)a.env_idx[i] : (int64_t)i;
     if (slot < 0 || slot >= a.n_slots) {
@@ -580,6 +580,9 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
     dyn_step(a.dyn, s, act, o);
     for (int k = 0; k < 17; ++k) a.state[slot * 17 + k] = o[k];
 }
+
+__global__ void __launch_bounds__(256) k_step(StepArgs a) { step_agent(a, blockIdx.x * blockDim.x + threadIdx.x); }
+
 
 // Copy state rows idx[i] -> out[i] (one thread per value).
 __global__ void k_gather_rows(const float* __restrict__ state, const int32_t* __restrict__ idx, int32_t n,
@@ -732,10 +735,12 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
     return kCostBuckets - 1 - (b < kCostBuckets - 1 ? b : kCostBuckets - 1);
 }
 
-__global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) {
+// One workgroup of the cost order: XCD range (block & 7), chunk (block >> 3); any workgroup size of at
+// least kCostBuckets threads.
+__device__ __forceinline__ void group_order_block(const GroupOrderArgs& a, int block) {
     __shared__ uint8_t bucket[kGroupOrderChunk];
     __shared__ int32_t off[kCostBuckets];
-    const int t = threadIdx.x, x = blockIdx.x & 7, chunk = blockIdx.x >> 3;
+    const int t = threadIdx.x, x = block & 7, chunk = block >> 3;
     const int q = a.total >> 3, r = a.total & 7;
     const int range = q + (x < r ? 1 : 0);
     const int begin = x * q + (x < r ? x : r) + chunk * kGroupOrderChunk;
@@ -766,11 +771,33 @@ __global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) {
     for (int i = t; i < size; i += blockDim.x) a.perm[atomicAdd(&off[bucket[i]], 1)] = begin + i;
 }
 
+__global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) { group_order_block(a, blockIdx.x); }
+
+// A split step's dynamics and the next render's cost order in one launch (the two do not depend on each
+// other): the first order_blocks workgroups sort, the rest step 256 agents each.
+__global__ void __launch_bounds__(256) k_step_order(StepArgs s, GroupOrderArgs g, int order_blocks) {
+    if ((int)blockIdx.x < order_blocks)
+        group_order_block(g, blockIdx.x);
+    else
+        step_agent(s, ((int)blockIdx.x - order_blocks) * 256 + threadIdx.x);
+}
+
+static int group_order_blocks(int32_t total) {
+    const int range = (total + 7) / 8;     // the largest XCD range
+    return 8 * ((range + kGroupOrderChunk - 1) / kGroupOrderChunk);
+}
+
 hipError_t launch_group_order(const GroupOrderArgs& a, hipStream_t st) {
     if (a.total <= 0 || a.total > kGroupOrderMax) return hipErrorInvalidValue;
-    const int range = (a.total + 7) / 8;     // the largest XCD range
-    const int chunks = (range + kGroupOrderChunk - 1) / kGroupOrderChunk;
-    hipLaunchKernelGGL(k_group_order, dim3(8 * chunks), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_group_order, dim3(group_order_blocks(a.total)), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_order(const StepArgs& s, const GroupOrderArgs& g, hipStream_t st) {
+    if (g.total <= 0 || g.total > kGroupOrderMax) return hipErrorInvalidValue;
+    const int ob = group_order_blocks(g.total);
+    const int sb = s.n > 0 ? (s.n + 255) / 256 : 0;
+    hipLaunchKernelGGL(k_step_order, dim3(ob + sb), dim3(256), 0, st, s, g, ob);
     return hipGetLastError();
 }
 

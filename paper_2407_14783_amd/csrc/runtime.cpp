@@ -422,22 +422,15 @@ static StreamScratch* scratch_for(vf_ctx* ctx, hipStream_t st) {
 // the render gains nothing measurable); the two are not combined: a cost-ordered launch gains nothing
 // from the spatial order, and its work estimates are kept per logical group, which the spatial order
 // would move between agents from one step to the next.
-static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
-    a.order = nullptr;
-    a.group_order = nullptr;
-    a.cost = nullptr;
+// The cost order of a split render: when the launch is eligible, a.cost gets the stream's work record (the
+// render writes its work there), and when the previous launch of this shape on the stream left work
+// estimates, *g holds the k_group_order arguments for a.group_order and the result is true.
+static bool plan_cost_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st, GroupOrderArgs* g) {
     const int32_t gpa = render_groups_per_agent(a.max_h, a.max_w);
     const int64_t total = (int64_t)a.n * gpa;
-    const bool by_cost = ctx->cost_order && total >= kGroupOrderMin && total <= kGroupOrderMax;
-    const bool spatial = !by_cost && ctx->spatial_order && a.n >= 64 && a.n <= kOrderAutoMax;
-    if (!spatial && !by_cost) return;
+    if (!(ctx->cost_order && total >= kGroupOrderMin && total <= kGroupOrderMax)) return false;
     StreamScratch* sc = scratch_for(ctx, st);
-    if (!sc) return;   // no memory for the scratch: plain order
-    if (spatial) {
-        OrderArgs o{a.n, a.env_idx, a.state, a.n_slots, a.views, sc->order};
-        if (launch_order(o, st) == hipSuccess) a.order = sc->order;
-    }
-    if (!by_cost) return;
+    if (!sc) return false;   // no memory for the scratch: plain order
     bool have_cost;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -445,11 +438,28 @@ static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
         sc->cost_n = a.n;
         sc->cost_groups = gpa;
     }
-    if (have_cost) {
-        GroupOrderArgs g{(int32_t)total, sc->cost, sc->perm};
-        if (launch_group_order(g, st) == hipSuccess) a.group_order = sc->perm;
-    }
     a.cost = sc->cost;
+    if (!have_cost) return false;
+    *g = GroupOrderArgs{(int32_t)total, sc->cost, sc->perm};
+    return true;
+}
+
+// Spatial order (agents of a launch by position) for launches that are not cost-ordered.
+static void maybe_spatial_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
+    if (a.cost || !(ctx->spatial_order && a.n >= 64 && a.n <= kOrderAutoMax)) return;
+    StreamScratch* sc = scratch_for(ctx, st);
+    if (!sc) return;
+    OrderArgs o{a.n, a.env_idx, a.state, a.n_slots, a.views, sc->order};
+    if (launch_order(o, st) == hipSuccess) a.order = sc->order;
+}
+
+static void maybe_order(vf_ctx* ctx, RenderArgs& a, hipStream_t st) {
+    a.order = nullptr;
+    a.group_order = nullptr;
+    a.cost = nullptr;
+    GroupOrderArgs g{};
+    if (plan_cost_order(ctx, a, st, &g) && launch_group_order(g, st) == hipSuccess) a.group_order = g.perm;
+    maybe_spatial_order(ctx, a, st);
 }
 
 // While swarms are set: the member trees of this stream (allocated once per vf_set_swarms generation),
@@ -537,10 +547,20 @@ vf_status vf_step(vf_ctx* ctx, const vf_dyn_params* params, int64_t n, const int
     if (ctx->swarm.n > 0) split = true;   // members must be read after every agent has stepped
     if (split) {
         StepArgs sa{(int32_t)n, env_idx, state, n_slots, action, ctx->d_err, dc};
-        VF_HIP(launch_step(sa, st));
+        // the cost order does not read the states: it runs in the dynamics' launch
+        a.order = nullptr;
+        a.group_order = nullptr;
+        a.cost = nullptr;
+        GroupOrderArgs g{};
+        if (plan_cost_order(ctx, a, st, &g)) {
+            VF_HIP(launch_step_order(sa, g, st));
+            a.group_order = g.perm;
+        } else {
+            VF_HIP(launch_step(sa, st));
+        }
         s = prepare_swarm(ctx, a, st);
         if (s != VF_OK) return s;
-        maybe_order(ctx, a, st);
+        maybe_spatial_order(ctx, a, st);
         VF_HIP(timed_render(ctx, a, false, st));
         return VF_OK;
     }

@@ -444,6 +444,8 @@ struct QueryArgs {
 };
 hipError_t launch_closest_point(const QueryArgs& q, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, hipStream_t st);
+// a split step's dynamics and the cost order of the render after it, in one launch
+hipError_t launch_step_order(const StepArgs& s, const GroupOrderArgs& g, hipStream_t st);
 hipError_t launch_render(RenderArgs a, bool fused, bool stats, bool noise, hipStream_t st);
 hipError_t launch_step_backward(const StepBackArgs& a, hipStream_t st);
 hipError_t launch_swarm_tree(const SwarmTable& sw, const float* state, int64_t n_slots, uint32_t* err,
