@@ -4,8 +4,9 @@
 // the 4-wide BVH together: every node and leaf triangle is fetched once per
 // wavefront through the scalar data path (wave-uniform address), each lane
 // tests its own ray, and ballots decide which children the packet visits.  The
-// traversal stack is wave-uniform and lives in two VGPRs, one entry per lane
-// (a lane-select write and v_readlane, the stack pointer in an SGPR).  Children are
+// traversal stack is wave-uniform and lives in VGPR lanes, one entry per lane (a
+// lane-select write and v_readlane, the stack pointer in an SGPR): one VGPR while every
+// resident BVH is at most kShallowDepth levels deep, two otherwise.  Children are
 // pushed far-to-near using the node's precomputed order for the packet's
 // direction octant, so the nearest child is popped first and lanes that have
 // found a closer hit cull the rest by their per-lane t.  The traversal is
@@ -19,8 +20,9 @@
 // kWavesPerBlock) groups.  Workgroups are remapped so
 // each XCD (workgroup id mod 8) processes a contiguous range of agents, keeping
 // one agent's (and, with agents grouped by scene, one scene's) traffic in one L2.  Within its range an
-// XCD may take the workgroups in an order given by k_group_order (longest packets first); every
-// wavefront reports its traversal work for the next launch's order.
+// XCD may take the workgroups in an order given by k_group_order, or by k_step_order together with a
+// split step's dynamics (longest packets first); every wavefront reports its traversal work for the next
+// launch's order.
 //
 // The fused kernel (vf_step with views) first advances the agent's dynamics in
 // one lane per workgroup (every workgroup of the agent computes the same bits),

@@ -66,7 +66,7 @@ constexpr int kWidthBits = kWidth == 4 ? 2 : 3;      // bits of a child slot ind
 // for one node, which 8 waves per SIMD cannot hold besides the rest
 constexpr int kRenderWavesPerEu = kWidth == 4 ? 8 : 6;
 constexpr int kFusedWavesPerEu = 2;   // the fused step + render (small batches: at most 1,024 workgroups)
-constexpr int kStackCap = 128;        // traversal stack entries per wavefront (2 VGPR lanes)
+constexpr int kStackCap = 128;        // traversal stack entries per wavefront (lanes of 2 VGPRs at most)
 // builds deeper than this are rejected: a packet keeps at most kWidth - 1 pending siblings per level
 constexpr int kMaxBvhDepth = kWidth == 4 ? 40 : 18;
 // a packet keeps at most kWidth - 1 pending siblings per level of its path plus the children just pushed
