@@ -492,6 +492,45 @@ def test_spatial_order_changes_nothing(vf):
         ctx.free_scene(sid)
 
 
+def test_step_with_cost_order_changes_nothing(vf):
+    """vf_step's split launches run the dynamics and the cost order in one launch (k_step_order): four steps
+    of 2,100 agents on permuted env slots of a larger table (the sort runs in two chunks per XCD) give the
+    same states, depth and ids with the order on and off."""
+    sim, ctx = vf
+    p = default_params()
+    sc = scenes.forest(seed=3, n_trees=300)
+    sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
+    n, slots, steps = 2100, 2600, 4
+    rng = np.random.default_rng(91)
+    table = agents.forest_starts(91, slots, sc, p)
+    idx = rng.permutation(slots)[:n].astype(np.int32)
+    acts = agents.random_actions(92, steps, n, p)
+    views, npx, offs, mh, mw = sim.make_views(n, sid, (64, 64))
+    header(f"step with cost order on/off: {n} agents on {slots} slots, {steps} steps")
+    outs = {}
+    try:
+        ctx.set_launch_mode(False)
+        for on in (True, False):
+            ctx.set_cost_order(on)
+            st = _dev(table)
+            depth = torch.full((npx,), float("nan")).cuda()
+            ids = torch.full((npx,), -7, dtype=torch.int32).cuda()
+            for k in range(steps):
+                ctx.step(p, st, _dev(acts[k]), views=views, env_idx=_dev(idx, torch.int32), max_hw=(mh, mw),
+                         depth=depth, tri_id=ids, out_pixels=npx)
+            ctx.sync_check()
+            outs[on] = (st.cpu().numpy(), depth.cpu().numpy(), ids.cpu().numpy())
+    finally:
+        ctx.set_cost_order(True)
+        ctx.set_launch_mode(None)
+    for a, b in zip(outs[True], outs[False]):
+        assert np.array_equal(a, b)
+    assert not np.isnan(outs[True][1]).any() and not (outs[True][2] == -7).any()
+    untouched = np.setdiff1d(np.arange(slots), idx)
+    assert np.array_equal(outs[True][0][untouched], table[untouched])
+    ctx.free_scene(sid)
+
+
 def test_cost_order_changes_nothing(vf):
     """Longest-first workgroup order (from the work the previous launch of the same shape reported)
     moves packets between workgroups only: repeated renders with it on and off, with launches of other
