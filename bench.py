@@ -320,22 +320,25 @@ def multi_scene_throughput(ctx, sim, params, steps=20, count=True):
 
 def alu_roofline(st, launches, render_s):
     """ALU roofline of the render kernel from the counting replay's counters over `launches` launches and
-    the average launch time render_s (HIP events over the timed region).  achieved = the launch's ray-box
-    and ray-triangle tests priced at OPS_PER_BOX / OPS_PER_TRI, over render_s; beside it the same tests at
-    the kernel's issued prices, and the tests a lane's own ray asked for (per-ray traversal need)."""
+    the average launch time render_s (HIP events over the timed region).  achieved = the algorithmic work of
+    the launch over render_s: the ray-box and ray-triangle tests each ray's own traversal needs (the visits
+    of nodes and leaves whose box that ray entered), priced at OPS_PER_BOX / OPS_PER_TRI.  Beside it the
+    tests the packets issue (every valid lane at every node and leaf its packet visits), at the same prices
+    and at the kernel's issued prices: their excess over the need is the packets' waste."""
     rays = st["rays"] / launches
     box, tri = st["box_lane"] / launches, st["tri_lane"] / launches
     nbox, ntri = st["need_box"] / launches, st["need_tri"] / launches
     ops = box * OPS_PER_BOX + tri * OPS_PER_TRI
     issued_ops = st["box_ops"] / launches + tri * ISSUED_OPS_PER_TRI
     need_ops = nbox * OPS_PER_BOX + ntri * OPS_PER_TRI
-    achieved = ops / render_s / 1e12
+    achieved = need_ops / render_s / 1e12
     logical = st["node_wave"] / launches * NODE_BYTES + st["tri_wave"] / launches * TRI_BYTES
     roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": ALU_UNIT,
             "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+            "work": "the tests each ray's own traversal needs, at the prices below",
             "prices": {"box_test": OPS_PER_BOX, "tri_test": OPS_PER_TRI},
-            "frac_at_issued_prices": issued_ops / render_s / 1e12 / ALU_PEAK_TOPS,
-            "frac_per_ray_need": need_ops / render_s / 1e12 / ALU_PEAK_TOPS,
+            "frac_issued_tests": ops / render_s / 1e12 / ALU_PEAK_TOPS,
+            "frac_issued_tests_at_issued_prices": issued_ops / render_s / 1e12 / ALU_PEAK_TOPS,
             "render_kernel_us": render_s * 1e6,
             "per_launch": {"rays": rays, "ray_box_tests": box, "ray_tri_tests": tri,
                            "wave_node_visits": st["node_wave"] / launches,
@@ -344,8 +347,10 @@ def alu_roofline(st, launches, render_s):
                            "needed_tri_tests_per_ray": ntri / max(rays, 1),
                            "packet_efficiency_box": nbox / max(box, 1), "packet_efficiency_tri": ntri / max(tri, 1),
                            "issued_valu_ops_per_box_test": st["box_ops"] / max(st["box_lane"], 1),
-                           "valu_ops": ops, "issued_valu_ops": issued_ops, "logical_scene_bytes": logical}}
+                           "valu_ops_needed": need_ops, "valu_ops_issued_tests": ops,
+                           "valu_ops_at_issued_prices": issued_ops, "logical_scene_bytes": logical}}
     rates = {"ray_box_tests_per_s": box / render_s, "ray_tri_tests_per_s": tri / render_s,
+             "needed_ray_box_tests_per_s": nbox / render_s, "needed_ray_tri_tests_per_s": ntri / render_s,
              "valu_ceiling_box_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_BOX,
              "valu_ceiling_tri_tests_per_s": ALU_PEAK_TOPS * 1e12 / OPS_PER_TRI,
              "logical_scene_GBps": logical / render_s / 1e9,
