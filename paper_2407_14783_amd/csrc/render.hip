@@ -578,6 +578,8 @@ __device__ __forceinline__ void step_agent(const StepArgs& a, int i) {
     }
     float s[17], act[4], o[17];
     for (int k = 0; k < 17; ++k) s[k] = a.state[slot * 17 + k];
+    if (a.before)
+        for (int k = 0; k < 17; ++k) a.before[(int64_t)i * 17 + k] = s[k];
     for (int k = 0; k < 4; ++k) act[k] = a.action[(int64_t)i * 4 + k];
     dyn_step(a.dyn, s, act, o);
     for (int k = 0; k < 17; ++k) a.state[slot * 17 + k] = o[k];

@@ -6,8 +6,8 @@
 // runs the admission logic of batcher.h (arrival order, arena bytes, no env slot in
 // two batches at once, max_batch_agents) over the server's stream slots.  The
 // batch's work list (views with output offsets, env slots, actions) goes to the
-// device in one copy; the batch snapshots its env slots' states, then the step
-// and render kernels run on the slot's stream and the outputs come back to pinned
+// device in one copy; the step kernel saves the env slots' states before it steps
+// them, the render kernel follows on the slot's stream and the outputs come back to pinned
 // host memory on the same stream.  Several slots are in flight at once, so batches
 // overlap on the device while new requests are admitted.  A batch that fails to
 // launch, or that the host reports failed (vf_server_inject_faults), has its env
@@ -193,16 +193,20 @@ struct HipBackend {
         }
         const int32_t* d_idx = (const int32_t*)(d + a.off_idx);
         hipError_t e = hipMemcpyAsync(d, h, a.off_before, hipMemcpyHostToDevice, a.stream);
-        // the slots' states before the step, for a batch that has to run again
-        if (e == hipSuccess) e = launch_gather_rows(s->state, d_idx, (int32_t)n, (float*)(d + a.off_before), a.stream);
+        if (e != hipSuccess) {
+            s->worker_error = std::string("batch launch: ") + hipGetErrorString(e);
+            return false;
+        }
+        uint32_t* d_err = (uint32_t*)d;
+        // the step also keeps the slots' states before it, for a batch that has to run again
+        StepArgs sa{(int32_t)n, d_idx, s->state, s->n_slots, (const float*)(d + a.off_act), d_err, s->dyn,
+                    (float*)(d + a.off_before)};
+        e = launch_step(sa, a.stream);
         if (e != hipSuccess) {
             s->worker_error = std::string("batch launch: ") + hipGetErrorString(e);
             return false;
         }
         a.snapshot = true;
-        uint32_t* d_err = (uint32_t*)d;
-        StepArgs sa{(int32_t)n, d_idx, s->state, s->n_slots, (const float*)(d + a.off_act), d_err, s->dyn};
-        e = launch_step(sa, a.stream);
         RenderArgs ra;
         memset(&ra, 0, sizeof(ra));
         ra.scenes = s->ctx->d_scenes;

@@ -355,6 +355,7 @@ struct StepArgs {
     const float* action;
     uint32_t* err;
     DynConstD dyn;
+    float* before;       // [n][17] the rows before the step (a batch that may run again), or NULL
 };
 struct StepBackArgs {
     int32_t n;
