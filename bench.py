@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--multi-scene-only", action="store_true",
                     help="run only the multi-scene batch and print its record (for counter runs)")
+    ap.add_argument("--differentiable-only", action="store_true",
+                    help="run only the differentiable rollout and print its record (for kernel traces)")
     ap.add_argument("--no-cost-order", action="store_true",
                     help="plain workgroup order (no longest-first order from the previous launch's work)")
     ap.add_argument("--no-spatial-order", action="store_true",
@@ -427,6 +429,12 @@ def main():
         from workloads import default_params
         ctx = sim.Context(0)
         print(json.dumps({"multi_scene": multi_scene_throughput(ctx, sim, default_params(), count=not args.no_stats)}))
+        ctx.close()
+        return
+    if args.differentiable_only:
+        from workloads import default_params
+        ctx = sim.Context(0)
+        print(json.dumps({"differentiable": bptt_throughput(ctx, sim, default_params())}))
         ctx.close()
         return
     from workloads import agents, default_params, scenes
