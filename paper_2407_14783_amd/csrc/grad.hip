@@ -17,8 +17,10 @@
 // k_render_backward (in FP64): depth t = n.(V0 - o) / n.d on the hit triangle's plane;
 // dt/do = -n / n.d, dt/dd = -t n / n.d, d = R(q/|q|) d_B with d_B = R_m d_cam and
 // o = p + R t_m for a camera mounted at (R_m, t_m).  Per agent the pixel
-// sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix) are reduced in
-// a fixed order (accumulated in FP64), then chained through R and the quaternion normalisation.
+// sums of grad * dt/do and of (grad * dt/dd) d_B^T (a 3x3 matrix, kept as three vector sums since d_B is
+// affine in the pixel's image-plane coordinates) are reduced in a fixed order (accumulated in FP64), then
+// chained through R and the quaternion normalisation.  One workgroup per agent; each thread has several
+// pixels' id, triangle and gradient loads in flight at once.
 #include "dynamics.h"
 #include "vf_internal.h"
 
@@ -404,10 +406,20 @@ __global__ void __launch_bounds__(kTangentThreads) k_step_backward_tangent(StepB
         a.grad_action[i * 4 + (j - 17)] = (float)g;
 }
 
-constexpr int kBackThreads = 256;
+// The workgroup's per-agent constants are the same in every lane: held in scalar registers they leave the
+// vector registers to the pixel batch.
+__device__ __forceinline__ double wave_uniform(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
-__global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs a) {
-    __shared__ double red[12][kBackThreads];
+constexpr int kBackThreads = 256;
+constexpr int kBackBatch = 2;   // pixels per thread whose id, triangle and gradient loads are in flight together
+
+__global__ void __launch_bounds__(kBackThreads) __attribute__((amdgpu_waves_per_eu(4))) k_render_backward(RenderBackArgs a) {
+    __shared__ double red[kBackThreads / 64][12];
     const int agent = blockIdx.x;
     vf_view vw = a.views[agent];
     bool ok = vw.scene_id >= 0 && vw.scene_id < a.n_scenes && vw.H >= 1 && vw.W >= 1 && vw.H <= a.max_h &&
@@ -433,63 +445,115 @@ __global__ void __launch_bounds__(kBackThreads) k_render_backward(RenderBackArgs
     double o[3];
     for (int i = 0; i < 3; ++i)
         o[i] = (double)st[i] + (rot[3 * i] * tm[0] + rot[3 * i + 1] * tm[1] + rot[3 * i + 2] * tm[2]);
+    // camera ray of pixel (r, c): d_cam = (1, -u, v), u and v affine in c and r with the same step du;
+    // world direction d = C0 - u C1 + v C2, column j of C = R R_m
     const double tan_h = tan(0.5 * (double)vw.hfov);
+    const double du = wave_uniform(2.0 * tan_h / (double)vw.W);
+    const double u0 = wave_uniform(0.5 * du - tan_h), v0 = wave_uniform(tan_h * (double)vw.H / (double)vw.W - 0.5 * du);
+    double C[3][3];   // C[j][i]: component i of column j
+    for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i)
+            C[j][i] = wave_uniform(rot[3 * i] * m[j] + rot[3 * i + 1] * m[3 + j] + rot[3 * i + 2] * m[6 + j]);
+    for (int i = 0; i < 3; ++i) o[i] = wave_uniform(o[i]);
+    // acc[0..2]: sum s_o n; acc[3..11]: sums of w n, w u n and w v n (w = s_d), from which
+    // sum w n d_cam^T follows because d_cam is affine in (u, v)
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     uint32_t bad = 0;
     const int npix = vw.H * vw.W;
-    // every pixel's terms in FP64: the pixel sums cancel to a small fraction of their terms for some
-    // directions (a roll turns one half of the image nearer and the other farther)
-    for (int pix = threadIdx.x; pix < npix; pix += kBackThreads) {
-        int64_t at = vw.out_offset + pix;
-        int32_t id = a.tri_id[at];
-        float g = a.grad_depth[at];
-        if (id < 0 || g == 0.0f) continue;
-        if (id >= sc.n_tris) {
-            if (vw.swarm <= 0) bad = kErrTriId;   // ids past the mesh name swarm members: no gradient
-            continue;
+    const int32_t* idp = a.tri_id + vw.out_offset;
+    const float* gp = a.grad_depth + vw.out_offset;
+    for (int base = threadIdx.x; base < npix; base += kBackBatch * kBackThreads) {
+        int32_t slot[kBackBatch];
+        float g[kBackBatch];
+#pragma unroll
+        for (int k = 0; k < kBackBatch; ++k) {
+            const int pix = base + k * kBackThreads;
+            int32_t id = -1;
+            g[k] = 0.0f;
+            if (pix < npix) {
+                id = idp[pix];
+                g[k] = gp[pix];
+            }
+            slot[k] = -1;
+            if (id >= 0 && g[k] != 0.0f) {
+                if (id < sc.n_tris)
+                    slot[k] = id;
+                else if (vw.swarm <= 0)
+                    bad = kErrTriId;   // ids past the mesh name swarm members: no gradient
+            }
         }
-        const Tri tr = sc.tris[sc.sorted_of[id]];
-        int r = pix / vw.W, cc = pix - r * vw.W;
-        const double u = (2.0 * ((double)cc + 0.5) / (double)vw.W - 1.0) * tan_h;
-        const double v = (1.0 - 2.0 * ((double)r + 0.5) / (double)vw.H) * tan_h * ((double)vw.H / (double)vw.W);
-        const double db[3] = {m[0] - m[1] * u + m[2] * v, m[3] - m[4] * u + m[5] * v, m[6] - m[7] * u + m[8] * v};
-        const double d[3] = {rot[0] * db[0] + rot[1] * db[1] + rot[2] * db[2],
-                             rot[3] * db[0] + rot[4] * db[1] + rot[5] * db[2],
-                             rot[6] * db[0] + rot[7] * db[1] + rot[8] * db[2]};
-        const double e1[3] = {tr.e1x, tr.e1y, tr.e1z}, e2[3] = {tr.e2x, tr.e2y, tr.e2z};
-        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                             e1[0] * e2[1] - e1[1] * e2[0]};
-        const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
-        if (nd == 0.0) continue;
-        const double t = (n[0] * ((double)tr.v0x - o[0]) + n[1] * ((double)tr.v0y - o[1]) +
-                          n[2] * ((double)tr.v0z - o[2])) / nd;
-        const double s_o = -(double)g / nd, s_d = -(double)g * t / nd;
-        for (int k = 0; k < 3; ++k) acc[k] += s_o * n[k];
-        for (int i2 = 0; i2 < 3; ++i2)
-            for (int j = 0; j < 3; ++j) acc[3 + 3 * i2 + j] += s_d * n[i2] * db[j];
+#pragma unroll
+        for (int k = 0; k < kBackBatch; ++k)
+            if (slot[k] >= 0) slot[k] = sc.sorted_of[slot[k]];
+        Tri tr[kBackBatch];
+#pragma unroll
+        for (int k = 0; k < kBackBatch; ++k)
+            if (slot[k] >= 0) tr[k] = sc.tris[slot[k]];
+#pragma unroll
+        for (int k = 0; k < kBackBatch; ++k) {
+            if (slot[k] < 0) continue;
+            const int pix = base + k * kBackThreads;
+            const int r = pix / vw.W, cc = pix - r * vw.W;
+            const double u = u0 + du * (double)cc, v = v0 - du * (double)r;
+            double d[3];
+            for (int i = 0; i < 3; ++i) d[i] = C[0][i] - u * C[1][i] + v * C[2][i];
+            const double e1[3] = {tr[k].e1x, tr[k].e1y, tr[k].e1z}, e2[3] = {tr[k].e2x, tr[k].e2y, tr[k].e2z};
+            const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                 e1[0] * e2[1] - e1[1] * e2[0]};
+            const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+            if (nd == 0.0) continue;
+            const double inv = 1.0 / nd;
+            const double t = (n[0] * ((double)tr[k].v0x - o[0]) + n[1] * ((double)tr[k].v0y - o[1]) +
+                              n[2] * ((double)tr[k].v0z - o[2])) * inv;
+            const double s_o = -(double)g[k] * inv, w = s_o * t;
+            for (int i = 0; i < 3; ++i) {
+                const double wn = w * n[i];
+                acc[i] += s_o * n[i];
+                acc[3 + i] += wn;
+                acc[6 + i] += wn * u;
+                acc[9 + i] += wn * v;
+            }
+        }
     }
     if (bad) atomicOr(a.err, bad);
-    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = acc[k];
+    // fixed-order reduction: butterfly within each wavefront, then the wavefronts in order
+    for (int k = 0; k < 12; ++k)
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 12; ++k) red[threadIdx.x >> 6][k] = acc[k];
     __syncthreads();
-    for (int s = kBackThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 12; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        // re-read after the barrier rather than keep them live through the pixel loop
+        const vf_view vw2 = a.views[agent];
+        const float* st2 = a.state + (int64_t)agent * 17;
+        const double q2[4] = {st2[3], st2[4], st2[5], st2[6]};
+        double m2[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+        if (!(vw2.mount_q[1] == 0.0f && vw2.mount_q[2] == 0.0f && vw2.mount_q[3] == 0.0f)) {
+            const double mq[4] = {vw2.mount_q[0], vw2.mount_q[1], vw2.mount_q[2], vw2.mount_q[3]};
+            body_rot(mq, m2);
+        }
+        const double tm2[3] = {vw2.mount_t[0], vw2.mount_t[1], vw2.mount_t[2]};
+        double S[12];
+        for (int k = 0; k < 12; ++k) {
+            S[k] = red[0][k];
+            for (int wv = 1; wv < kBackThreads / 64; ++wv) S[k] += red[wv][k];
+        }
         float* gs = a.grad_state + (int64_t)agent * 17;
-        for (int k = 0; k < 3; ++k) gs[k] += (float)red[k][0];
+        for (int k = 0; k < 3; ++k) gs[k] += (float)S[k];
+        // G = sum w n d_B^T with d_B = R_m d_cam: column j of d_B is m[3j] - u m[3j+1] + v m[3j+2]
         double G[9];
-        for (int k = 0; k < 9; ++k) G[k] = red[3 + k][0];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                G[3 * i + j] = S[3 + i] * m2[3 * j] - S[6 + i] * m2[3 * j + 1] + S[9 + i] * m2[3 * j + 2];
         // the origin p + R t_m also moves with R
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) G[3 * i + j] += red[i][0] * tm[j];
-        const double inv = 1.0 / sqrt(qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
-        const double qn[4] = {qd[0] * inv, qd[1] * inv, qd[2] * inv, qd[3] * inv};
+            for (int j = 0; j < 3; ++j) G[3 * i + j] += S[i] * tm2[j];
+        const double inv = 1.0 / sqrt(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2] + q2[3] * q2[3]);
+        const double qn[4] = {q2[0] * inv, q2[1] * inv, q2[2] * inv, q2[3] * inv};
         double lqn[4], lq[4];
         rot_vjp(qn, G, lqn);
-        normalize_vjp(qd, lqn, lq);
+        normalize_vjp(q2, lqn, lq);
         for (int k = 0; k < 4; ++k) gs[3 + k] += (float)lq[k];
     }
 }
