@@ -741,6 +741,7 @@ __device__ __forceinline__ int cost_bucket(uint32_t c) {
 
 // One workgroup of the cost order: XCD range (block & 7), chunk (block >> 3); any workgroup size of at
 // least kCostBuckets threads.
+constexpr int kOrderBatch = 8;
 __device__ __forceinline__ void group_order_block(const GroupOrderArgs& a, int block) {
     __shared__ uint8_t bucket[kGroupOrderChunk];
     __shared__ int32_t off[kCostBuckets];
@@ -752,15 +753,28 @@ __device__ __forceinline__ void group_order_block(const GroupOrderArgs& a, int b
     const int size = left < kGroupOrderChunk ? left : kGroupOrderChunk;      // <= 0: nothing to sort
     if (t < kCostBuckets) off[t] = 0;
     __syncthreads();
-    for (int i = t; i < size; i += blockDim.x) {
-        uint32_t c = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            const uint32_t cw = (uint32_t)a.cost[(int64_t)(begin + i) * kWavesPerBlock + w];
-            c = c + cw < c ? 0xFFFFFFFFu : c + cw;
+    // kOrderBatch groups' cost loads in flight per thread, then their buckets
+    for (int i0 = t; i0 < size; i0 += kOrderBatch * (int)blockDim.x) {
+        uint32_t c[kOrderBatch];
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            c[u] = 0;
+            if (i < size)
+                for (int w = 0; w < kWavesPerBlock; ++w) {
+                    const uint32_t cw = (uint32_t)a.cost[(int64_t)(begin + i) * kWavesPerBlock + w];
+                    c[u] = c[u] + cw < c[u] ? 0xFFFFFFFFu : c[u] + cw;
+                }
         }
-        const int b = cost_bucket(c);
-        bucket[i] = (uint8_t)b;
-        atomicAdd(&off[b], 1);
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < size) {
+                const int b = cost_bucket(c[u]);
+                bucket[i] = (uint8_t)b;
+                atomicAdd(&off[b], 1);
+            }
+        }
     }
     __syncthreads();
     if (t == 0) {
@@ -772,7 +786,17 @@ __device__ __forceinline__ void group_order_block(const GroupOrderArgs& a, int b
         }
     }
     __syncthreads();
-    for (int i = t; i < size; i += blockDim.x) a.perm[atomicAdd(&off[bucket[i]], 1)] = begin + i;
+    for (int i0 = t; i0 < size; i0 += kOrderBatch * (int)blockDim.x) {
+        int slot[kOrderBatch];
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            slot[u] = i < size ? atomicAdd(&off[bucket[i]], 1) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u)
+            if (slot[u] >= 0) a.perm[slot[u]] = begin + i0 + u * (int)blockDim.x;
+    }
 }
 
 __global__ void __launch_bounds__(1024) k_group_order(GroupOrderArgs a) { group_order_block(a, blockIdx.x); }
