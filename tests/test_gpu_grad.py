@@ -117,13 +117,15 @@ def test_step_backward_matches_fd_jacobian(vf, variant):
             assert np.linalg.norm(ga[i]) <= 1e-5
 
 
-def test_render_backward_matches_fd(vf):
+@pytest.mark.parametrize("h,w", [(16, 16), (12, 20), (40, 26)])
+def test_render_backward_matches_fd(vf, h, w):
+    """Square and non-square views; 40 x 26 spans two pixel batches of a workgroup and a ragged third."""
     sim, ctx = vf
     p = default_params()
     sc = scenes.box_room(seed=1)
     sid = ctx.build_scene(sc["verts"], sc["tris"], sc["rgb"])
     rng = np.random.default_rng(31)
-    n, h, w = 4, 16, 16
+    n = 4
     q = rng.normal(size=(n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
     st = agents.make_states(rng.uniform([1, 1, 0.5], [9, 9, 3.5], size=(n, 3)), p, quat=q)
@@ -139,7 +141,7 @@ def test_render_backward_matches_fd(vf):
         g[offs[i]:offs[i] + h * w][ref["mask"].reshape(-1)] = 0.0
     base = rng.normal(size=(n, 17)).astype(np.float32)
     grad_state = _dev(base)
-    header("render_backward: box room, 4 agents, 16x16")
+    header(f"render_backward: box room, 4 agents, {h}x{w}")
     ctx.render_backward(_dev(st), views, (mh, mw), ids, _dev(g), npx, grad_state)
     ctx.sync_check()
     got = grad_state.cpu().numpy() - base
