@@ -10,13 +10,15 @@ from .capi import check, lib
 
 
 def _ptr(t):
+    """Device address of a contiguous device tensor, as an integer (every entry point declares its pointer
+    arguments as void*, so ctypes passes it at full width)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
-    return ctypes.c_void_p(t.data_ptr())
+    return t.data_ptr()
 
 
 def _check_views(views, n):
@@ -30,9 +32,17 @@ def _check_rows(t, n, cols, name):
         raise ValueError(f"{name} holds fewer than {n} x {cols} values")
 
 
+# The current stream's raw handle without building a torch Stream object (that costs a few microseconds per
+# call, as much as a small step's whole launch); the public route where the raw getter is absent.
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(stream):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return stream.cuda_stream
+    if _raw_stream is not None:
+        return _raw_stream(torch.cuda.current_device())
+    return torch.cuda.current_stream().cuda_stream
 
 
 def make_views(n, scene_ids, hw, hfov=np.pi / 2, near=0.01, far=100.0, miss_depth=None, device="cuda",
