@@ -384,8 +384,9 @@ static hipError_t timed_render(vf_ctx* ctx, const RenderArgs& a, bool fused, hip
     }
     hipError_t e = hipSuccess;
     if (!ev.first) {
-        e = hipEventCreate(&ev.first);
-        if (e == hipSuccess) e = hipEventCreate(&ev.second);
+        // timing only: no system-scope fence (cache write-back and invalidation) at each record
+        e = hipEventCreateWithFlags(&ev.first, hipEventDisableSystemFence);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev.second, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
     }
     e = hipEventRecord(ev.first, st);
